@@ -1,0 +1,532 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against a closed form, an exact identity, a discrete
+dispersion relation or an invariant — never against a re-typed copy of the
+formula it tests.  The set is chosen so that a dropped term, a wrong sign or
+index, or a transposed operand in any part of the step fails at least one of
+them (tests/test_oracle_mutations.py plants such mistakes and checks that).
+"""
+import numpy as np
+import pytest
+
+from oracle import tfan_oracle as O
+from paper_2511_00445_amd.workloads import base_params, initial_fields, random_velocity
+
+C = O.CI.astype(np.float64)
+
+
+def _fresh(p, phi, qxx, qxy, u_a=None, u_p=None):
+    o = O.Oracle(p)
+    o.init_fields(phi, qxx, qxy, u_a=u_a, u_p=u_p)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# P1, P2: D2Q9 equilibrium and Guo source moments (Numerical Simulation)
+# ---------------------------------------------------------------------------
+def test_p1_equilibrium_moments():
+    rng = np.random.default_rng(10)
+    rho = 1.0 + 0.1 * rng.standard_normal((5, 7))
+    u = 0.05 * rng.standard_normal((2, 5, 7))
+    feq = O.equilibrium(rho, u)
+    np.testing.assert_allclose(feq.sum(0), rho, rtol=0, atol=1e-14)
+    for a in range(2):
+        np.testing.assert_allclose((feq * C[:, a, None, None]).sum(0), rho * u[a], rtol=0, atol=1e-14)
+        for b in range(2):
+            pi_ab = (feq * (C[:, a] * C[:, b])[:, None, None]).sum(0)
+            np.testing.assert_allclose(pi_ab, rho * (a == b) / 3.0 + rho * u[a] * u[b], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.7])
+def test_p2_guo_source_moments(tau):
+    rng = np.random.default_rng(11)
+    u = 0.05 * rng.standard_normal((2, 4, 6))
+    F = 1e-3 * rng.standard_normal((2, 4, 6))
+    S = O.guo_source(u, F, tau)
+    k = 1.0 - 0.5 / tau
+    np.testing.assert_allclose(S.sum(0), 0.0, atol=1e-17)
+    for a in range(2):
+        np.testing.assert_allclose((S * C[:, a, None, None]).sum(0), k * F[a], rtol=1e-13, atol=1e-18)
+        for b in range(2):
+            m2 = (S * (C[:, a] * C[:, b])[:, None, None]).sum(0)
+            np.testing.assert_allclose(m2, k * (u[a] * F[b] + F[a] * u[b]), rtol=1e-12, atol=1e-18)
+
+
+# ---------------------------------------------------------------------------
+# P3: per-fluid mass is exact; one step changes each fluid's momentum by its force
+# ---------------------------------------------------------------------------
+def test_p3_mass_and_momentum_balance():
+    p = base_params(24, 20, zeta=0.02, gamma=0.3)
+    ic = initial_fields(24, 20, seed=3, phi_mean=0.1, phi_noise=0.3)
+    o = _fresh(p, **ic, u_a=random_velocity(24, 20, 4), u_p=random_velocity(24, 20, 5))
+    o.step(3)
+    mac = o.macroscopic()
+    m_a0, m_p0 = mac["m_a"].sum((1, 2)), mac["m_p"].sum((1, 2))
+    mass_a0, mass_p0 = mac["rho_a"].sum(), mac["rho_p"].sum()
+    Fa, Fp = mac["F_a"].sum((1, 2)), mac["F_p"].sum((1, 2))
+    # drag is an exchange: it cancels in the total
+    np.testing.assert_allclose(Fa + Fp, (mac["G_a"] + mac["G_p"]).sum((1, 2)), atol=1e-15)
+    o.step(1)
+    mac1 = o.macroscopic()
+    assert abs(mac1["rho_a"].sum() - mass_a0) < 1e-11
+    assert abs(mac1["rho_p"].sum() - mass_p0) < 1e-11
+    np.testing.assert_allclose(mac1["m_a"].sum((1, 2)), m_a0 + Fa, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(mac1["m_p"].sum((1, 2)), m_p0 + Fp, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# P4: shear wave decays at nu k^2 with nu = (tau - 1/2)/3
+# ---------------------------------------------------------------------------
+def test_p4_shear_wave_viscosity():
+    N, tau_a, tau_p = 64, 1.0, 0.8
+    p = base_params(8, N, zeta=0.0, gamma=0.0, lam=0.0, tau_a=tau_a, tau_p=tau_p)
+    y = np.arange(N)[:, None] * np.ones((1, 8))
+    mode = np.sin(2 * np.pi * y / N)
+    u0 = np.array([1e-3 * mode, 0 * y])
+    z = np.zeros((N, 8))
+    o = _fresh(p, z, z, z, u_a=u0, u_p=u0)
+    amp = {"u_a": [], "u_p": []}
+    for t in range(101):
+        f = o.get_fields()
+        for key in amp:
+            amp[key].append((f[key][0] * mode).sum() / (mode ** 2).sum())
+        o.step(1)
+    k = 2 * np.pi / N
+    for key, tau in (("u_a", tau_a), ("u_p", tau_p)):
+        a = np.array(amp[key])
+        rate = np.log(a[20] / a[100]) / 80.0
+        nu = (tau - 0.5) / 3.0
+        # O(k^2) lattice correction is ~5e-4 at tau = 0.8, ~2e-7 at tau = 1
+        assert abs(rate / (nu * k * k) - 1.0) < 1e-3, (key, rate, nu * k * k)
+
+
+# ---------------------------------------------------------------------------
+# P5: implicit drag is the trapezoid rule: dm -> dm (1 - beta)/(1 + beta) per step
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("phibar,gamma", [(0.0, 0.01), (0.4, 0.5), (-0.6, 2.0)])
+def test_p5_drag_trapezoid(phibar, gamma):
+    n = 8
+    p = base_params(n, n, zeta=0.0, gamma=gamma)
+    U = np.array([3e-3, -1e-3])
+    ua = U[:, None, None] * np.ones((2, n, n))
+    z = np.zeros((n, n))
+    o = _fresh(p, z + phibar, z, z, u_a=ua, u_p=None)
+    beta = gamma * 0.25 * (1 + phibar) * (1 - phibar)
+    r = (1 - beta) / (1 + beta)
+    mac = o.macroscopic()
+    dm0 = (mac["m_a"] - mac["m_p"])[:, 0, 0]
+    tot0 = (mac["m_a"] + mac["m_p"])[:, 0, 0]
+    for t in range(1, 11):
+        o.step(1)
+        mac = o.macroscopic()
+        np.testing.assert_allclose((mac["m_a"] - mac["m_p"])[:, 0, 0], dm0 * r ** t, rtol=1e-11, atol=1e-16)
+        np.testing.assert_allclose((mac["m_a"] + mac["m_p"])[:, 0, 0], tot0, rtol=0, atol=1e-15)
+    # Guo velocity: u_a - u_p = dm / (1 + beta) at rho = 1
+    np.testing.assert_allclose((mac["u_a"] - mac["u_p"])[:, 0, 0], dm0 * r ** 10 / (1 + beta), rtol=0, atol=5e-16)
+
+
+# ---------------------------------------------------------------------------
+# P6: the flat interface phi = tanh(x / w), w = sqrt(2 kappa / A), is stationary
+# ---------------------------------------------------------------------------
+def _two_interfaces(nx, ny, w):
+    x = np.arange(nx) + 0.5
+    return np.tile(np.tanh((x - nx / 4) / w) * np.tanh((3 * nx / 4 - x) / w), (ny, 1))
+
+
+def test_p6_tanh_interface_chemical_potential():
+    # mu of the continuum equilibrium profile vanishes up to the O(kappa / w^4)
+    # truncation of the 5-point Laplacian: halving 1/w cuts it ~16x
+    A = 0.04
+    res = []
+    for kappa in (0.64, 2.56):
+        w = np.sqrt(2 * kappa / A)
+        mu = O.chemical_potential(_two_interfaces(256, 4, w), A, kappa)
+        res.append(np.abs(mu).max() * w ** 4 / kappa)
+    assert res[0] < 0.5 and 0.8 < res[1] / res[0] < 1.25, res
+    # a profile of the wrong width is far from equilibrium
+    w = np.sqrt(2 * 0.64 / A)
+    mu_bad = O.chemical_potential(_two_interfaces(128, 4, w * 1.25), A, 0.64)
+    assert np.abs(mu_bad).max() > 0.1 * A
+
+
+def test_p6_tanh_interface_stationary_under_dynamics():
+    A, kappa = 0.04, 0.16
+    w = np.sqrt(2 * kappa / A)
+    nx, ny = 96, 4
+    phi0 = _two_interfaces(nx, ny, w)
+    z = np.zeros((ny, nx))
+    o = _fresh(base_params(nx, ny, A_ch=A, kappa=kappa, zeta=0.0), phi0, z, z)
+    o.step(300)
+    # discrete equilibrium differs from the continuum profile by O(1/w^2) ~ 7e-3 here
+    assert np.abs(o.phi - phi0).max() < 1.2e-2
+    assert o.diagnostics()["umax"] < 5e-4
+
+
+# ---------------------------------------------------------------------------
+# P7: linear Cahn-Hilliard growth of a Fourier mode (discrete dispersion relation)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("phibar,mode,gamma", [(0.0, (4, 0), 0.01), (0.3, (2, 3), 0.01),
+                                               (-0.8, (1, 1), 0.5), (0.5, (5, 2), 2.0)])
+def test_p7_ch_linear_growth(phibar, mode, gamma):
+    """First step from rest, to linear order in eps.  Per sub-step the CH operator
+    multiplies the mode by g = 1 + h M lam_k D_k, D_k = A(3 phibar^2 - 1) - kappa lam_k.
+    When phibar != 0 the capillary force -phi grad(mu) is linear in eps, and the Guo
+    half-force velocity of the first step, u_c = alpha F_ch with
+    alpha = (c1^2 + c2^2 + g_d) / (2 (1 + 2 g_d)), g_d = gamma c1 c2 / 2, advects phi:
+    it adds b = -h alpha phibar^2 s_k D_k times the start-of-step amplitude per
+    sub-step, s_k = sin^2 kx + sin^2 ky (central differences)."""
+    N = 32
+    p = base_params(N, N, zeta=0.0, gamma=gamma)
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    eps = 1e-7
+    arg = 2 * np.pi * (mode[0] * x + mode[1] * y) / N
+    z = np.zeros((N, N))
+    o = _fresh(p, phibar + eps * np.cos(arg), z, z)
+    o.step(1)
+    kx, ky = 2 * np.pi * mode[0] / N, 2 * np.pi * mode[1] / N
+    lam_k = -4 * np.sin(kx / 2) ** 2 - 4 * np.sin(ky / 2) ** 2
+    s_k = np.sin(kx) ** 2 + np.sin(ky) ** 2
+    h, n = 1.0 / p["n_sub"], p["n_sub"]
+    D = p["A_ch"] * (3 * phibar ** 2 - 1) - p["kappa"] * lam_k
+    c1, c2 = (1 + phibar) / 2, (1 - phibar) / 2
+    gd = gamma * c1 * c2 / 2
+    alpha = (c1 ** 2 + c2 ** 2 + gd) / (2 * (1 + 2 * gd))
+    g = 1 + h * p["M"] * lam_k * D
+    b = -h * alpha * phibar ** 2 * s_k * D
+    expect = g ** n + b * (g ** n - 1) / (g - 1)
+    amp = ((o.phi - o.phi.mean()) * np.cos(arg)).sum() / (np.cos(arg) ** 2).sum()
+    assert abs(amp / eps - expect) < 1e-6 * abs(expect - 1) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P8: sum(phi) is exact on the periodic grid (flux-form central differences)
+# ---------------------------------------------------------------------------
+def test_p8_phi_mass_conserved():
+    p = base_params(32, 24, zeta=0.02)
+    ic = initial_fields(32, 24, seed=8, phi_mean=0.2, phi_noise=0.5)
+    o = _fresh(p, **ic, u_a=random_velocity(32, 24, 9, 1e-2), u_p=random_velocity(32, 24, 10, 1e-2))
+    s0 = o.phi.sum()
+    o.step(30)
+    assert abs(o.phi.sum() - s0) < 1e-12 * o.phi.size
+
+
+# ---------------------------------------------------------------------------
+# P9: uniform Q relaxes by S <- S [1 - h Gamma (A + C S^2)], S_eq = sqrt(-A/C)
+# ---------------------------------------------------------------------------
+def test_p9_ldg_relaxation_recurrence():
+    n = 8
+    p = base_params(n, n, zeta=0.0, A0=0.1, gamma_ldg=6.0)
+    S, theta = 0.05, 0.3
+    z = np.zeros((n, n))
+    o = _fresh(p, z, z + S * np.cos(2 * theta), z + S * np.sin(2 * theta))
+    h = 1.0 / p["n_sub"]
+    s = S
+    for t in range(40):
+        o.step(1)
+        for _ in range(p["n_sub"]):
+            s = s * (1 - h * p["Gamma"] * (p["A_ldg"] + p["C_ldg"] * s * s))
+        got = np.sqrt(o.qxx ** 2 + o.qxy ** 2)
+        np.testing.assert_allclose(got, s, rtol=1e-13)
+        np.testing.assert_allclose(np.arctan2(o.qxy, o.qxx), 2 * theta, atol=1e-13)
+    o.step(3000)
+    # uniaxial equilibrium order sqrt((gamma - 3) / (6 gamma)) = 0.288675 at gamma = 6
+    np.testing.assert_allclose(np.sqrt(o.qxx ** 2 + o.qxy ** 2), np.sqrt(3 / 36), rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# P10, P11: co-rotation term: symmetric with trace lam tr(W); rotation under shear
+# ---------------------------------------------------------------------------
+def test_p10_corotation_symmetric_with_trace():
+    rng = np.random.default_rng(12)
+    W = rng.standard_normal((2, 2, 5, 5))
+    Q = O.q_tensor(*(0.3 * rng.standard_normal((2, 5, 5))))
+    for lam in (0.0, 0.7, 2.0):
+        S = O.corotation(W, Q, lam)
+        np.testing.assert_allclose(S[0, 1], S[1, 0], atol=1e-14)
+        np.testing.assert_allclose(S[0, 0] + S[1, 1], lam * (W[0, 0] + W[1, 1]), atol=1e-14)
+
+
+@pytest.mark.parametrize("lam,S", [(0.0, 0.1), (0.7, 0.1), (0.7, 0.5), (2.0, 0.3)])
+def test_p11_director_rotation_in_simple_shear(lam, S):
+    # u_x = gdot * y: W_xy = d_y u_x = gdot.  The director angle obeys
+    # d(2 theta)/dt = gdot [lam cos(2 theta) / (2 S) - 1]; at lam = 0 it turns with
+    # the fluid at half the vorticity (clockwise for gdot > 0).
+    gdot = 1e-2
+    theta = np.linspace(0, np.pi, 13)[:-1]
+    W = np.zeros((2, 2, 1, theta.size))
+    W[0, 1] = gdot
+    Q = O.q_tensor(S * np.cos(2 * theta)[None], S * np.sin(2 * theta)[None])
+    Rxx, Rxy = O.project_sym_traceless(O.corotation(W, Q, lam))
+    qxx, qxy = Q[0, 0], Q[0, 1]
+    dtheta = (qxx * Rxy - qxy * Rxx) / (2 * S * S)
+    np.testing.assert_allclose(2 * dtheta[0], gdot * (lam * np.cos(2 * theta) / (2 * S) - 1), atol=1e-15)
+    # and the order changes as dS/dt = (lam gdot / 2) sin(2 theta) (1 - 4 S^2)
+    dS = (qxx * Rxx + qxy * Rxy) / S
+    np.testing.assert_allclose(dS[0], 0.5 * lam * gdot * np.sin(2 * theta) * (1 - 4 * S * S), atol=1e-16)
+
+
+def test_p11b_extension_orders_rods():
+    # u = (e x, -e y): rods (lam > 0) order along x at rate lam e (1 - 4 S^2)
+    e, lam = 1e-2, 0.7
+    W = np.zeros((2, 2, 1, 3))
+    W[0, 0], W[1, 1] = e, -e
+    S = np.array([[0.0, 0.1, 0.3]])
+    Rxx, Rxy = O.project_sym_traceless(O.corotation(W, O.q_tensor(S, 0 * S), lam))
+    np.testing.assert_allclose(Rxx, lam * e * (1 - 4 * S ** 2), atol=1e-16)
+    np.testing.assert_allclose(Rxy, 0.0, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------
+# P12: 2D identity used by compact implementations: H.P + P.H = (H:Q) I + H
+# ---------------------------------------------------------------------------
+def test_p12_elastic_stress_2d_identity():
+    rng = np.random.default_rng(13)
+    Q = O.q_tensor(*(0.2 * rng.standard_normal((2, 6, 6))))
+    H = O.q_tensor(*(0.1 * rng.standard_normal((2, 6, 6))))
+    P = Q + 0.5 * O.eye_field((6, 6))
+    lhs = O.mm(H, P) + O.mm(P, H)
+    rhs = O.ddot(H, Q) * O.eye_field((6, 6)) + H
+    np.testing.assert_allclose(lhs, rhs, atol=1e-15)
+    # and the molecular field is symmetric traceless, with the cubic (B) term inert in 2D
+    Qf = O.q_tensor(*(0.2 * rng.standard_normal((2, 6, 6))))
+    H0 = O.molecular_field(Qf, 0.03, 0.6, 0.04, B=0.0)
+    H1 = O.molecular_field(Qf, 0.03, 0.6, 0.04, B=-0.3)
+    np.testing.assert_allclose(H0, H1, atol=1e-15)
+    np.testing.assert_allclose(H0[0, 0] + H0[1, 1], 0.0, atol=1e-15)
+    np.testing.assert_allclose(H0[0, 1], H0[1, 0], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P13: linear relaxation of a small Q mode (lam = zeta = 0 decouples the flow)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode,comp", [((3, 0), 0), ((1, 2), 1)])
+def test_p13_q_mode_relaxation(mode, comp):
+    N = 24
+    p = base_params(N, N, zeta=0.0, lam=0.0, A0=0.1, gamma_ldg=1.0)
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    arg = 2 * np.pi * (mode[0] * x + mode[1] * y) / N
+    eps = 1e-7
+    q = [np.zeros((N, N)), np.zeros((N, N))]
+    q[comp] = eps * np.cos(arg)
+    o = _fresh(p, np.zeros((N, N)), q[0], q[1])
+    o.step(2)
+    lam_k = -4 * np.sin(np.pi * mode[0] / N) ** 2 - 4 * np.sin(np.pi * mode[1] / N) ** 2
+    h = 1.0 / p["n_sub"]
+    g = (1 + h * p["Gamma"] * (-p["A_ldg"] + p["K"] * lam_k)) ** (2 * p["n_sub"])
+    got = (o.qxx, o.qxy)[comp]
+    amp = (got * np.cos(arg)).sum() / (np.cos(arg) ** 2).sum()
+    assert abs(amp / eps - g) < 1e-6 * abs(1 - g)
+
+
+# ---------------------------------------------------------------------------
+# P14: passive (zeta = 0) total energy never increases
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lam", [0.7, 2.0])
+def test_p14_passive_energy_decays(lam):
+    n = 32
+    p = base_params(n, n, zeta=0.0, lam=lam, gamma=0.1, K=0.04, A0=0.1, gamma_ldg=4.0)
+    ic = initial_fields(n, n, seed=14, phi_mean=0.0, phi_noise=0.6, S0=0.25)
+    o = _fresh(p, **ic)
+    energies = [o.free_energy()]
+    for _ in range(40):
+        o.step(2)
+        energies.append(o.free_energy())
+    e = np.array(energies)
+    assert np.all(np.diff(e) <= 1e-9 * abs(e[0])), np.diff(e).max()
+    assert e[-1] < 0.9 * e[0]
+
+
+# ---------------------------------------------------------------------------
+# P15: single-fluid limit phi = 1, gamma = 0: the passive fluid decouples exactly
+# ---------------------------------------------------------------------------
+def test_p15_single_fluid_limit():
+    n = 16
+    p = base_params(n, n, gamma=0.0, zeta=0.05)
+    ic = initial_fields(n, n, seed=15, S0=0.3)
+    o = _fresh(p, np.ones((n, n)), ic["qxx"], ic["qxy"])
+    mac = o.macroscopic()
+    assert np.abs(mac["F_p"]).max() == 0.0 and np.abs(mac["u_p"]).max() == 0.0
+    fp0 = o.f_p.copy()
+    o.step(1)
+    np.testing.assert_allclose(o.f_p, fp0, rtol=0, atol=1e-15)
+    assert o.get_fields()["u_a"].std() > 1e-6   # the active fluid does move
+
+
+# ---------------------------------------------------------------------------
+# P16: uniform flow advects phi and Q in the flow direction (central-difference
+# phase, complex amplification per sub-step)
+# ---------------------------------------------------------------------------
+def _mode_coeff(g, mode):
+    N = g.shape[0]
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    e = np.exp(-2j * np.pi * (mode[0] * x + mode[1] * y) / N)
+    return (g * e).sum() / g.size
+
+
+@pytest.mark.parametrize("field", ["phi", "qxx"])
+def test_p16_uniform_advection(field):
+    N, mode = 32, (2, 1)
+    U = np.array([0.02, -0.01])
+    p = base_params(N, N, zeta=0.0, lam=0.0, gamma=0.3, A0=0.1, gamma_ldg=1.0)
+    x = np.arange(N)[None, :]
+    y = np.arange(N)[:, None]
+    eps = 1e-7
+    wave = eps * np.cos(2 * np.pi * (mode[0] * x + mode[1] * y) / N)
+    z = np.zeros((N, N))
+    uu = U[:, None, None] * np.ones((2, N, N))
+    phi, qxx = (wave, z) if field == "phi" else (z, wave)
+    o = _fresh(p, phi, qxx, z, u_a=uu, u_p=uu)
+    c0 = _mode_coeff(getattr(o, field), mode)
+    o.step(1)
+    c1 = _mode_coeff(getattr(o, field), mode)
+    kx, ky = 2 * np.pi * mode[0] / N, 2 * np.pi * mode[1] / N
+    lam_k = -4 * np.sin(kx / 2) ** 2 - 4 * np.sin(ky / 2) ** 2
+    adv = -1j * (U[0] * np.sin(kx) + U[1] * np.sin(ky))
+    if field == "phi":
+        lin = p["M"] * lam_k * (-p["A_ch"] - p["kappa"] * lam_k)
+    else:
+        lin = p["Gamma"] * (-p["A_ldg"] + p["K"] * lam_k)
+    g = (1 + (adv + lin) / p["n_sub"]) ** p["n_sub"]
+    assert abs(c1 / c0 - g) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Active stress sign: zeta > 0 is extensile (pushes fluid out along the director)
+# ---------------------------------------------------------------------------
+def test_active_stress_is_extensile():
+    n = 32
+    p = base_params(n, n, zeta=0.05, lam=0.0, K=0.0, gamma=0.0)
+    x = np.arange(n)[None, :] * np.ones((n, 1))
+    blob = 0.3 * np.exp(-((x - 16) / 4.0) ** 2)          # director along x in a band
+    o = _fresh(p, np.zeros((n, n)), blob, np.zeros((n, n)))
+    Fx = o.macroscopic()["G_a"][0][0]
+    assert Fx[22] > 0 and Fx[10] < 0                       # outward on both sides
+    d = np.arange(1, 12)
+    np.testing.assert_allclose(Fx[16 + d], -Fx[16 - d], atol=1e-15)  # mirror-antisymmetric
+
+
+# ---------------------------------------------------------------------------
+# Host analysis: single Fourier modes give exact lengths and spectra
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 3, 8])
+def test_domain_length_single_mode(n):
+    N = 64
+    x = np.arange(N)[None, :] * np.ones((N, 1))
+    phi = 0.7 * np.cos(2 * np.pi * n * x / N)
+    assert abs(O.domain_length(phi) - N / n) < 1e-12 * N
+
+
+def test_energy_spectrum_parseval_and_shell():
+    N = 64
+    rng = np.random.default_rng(16)
+    u = rng.standard_normal((2, N, N))
+    E = O.energy_spectrum(u)
+    assert abs(E.sum() - 0.5 * (u ** 2).sum(0).mean()) < 1e-12
+    y = np.arange(N)[:, None] * np.ones((1, N))
+    E1 = O.energy_spectrum(np.array([np.sin(2 * np.pi * 5 * y / N), 0 * y]))
+    assert abs(E1[5] - 0.25) < 1e-14 and abs(E1.sum() - 0.25) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P18: nematic body force of a director pattern theta(x) at constant S against
+# its hand-derived continuum value (second-order convergence), and the exact
+# diagonal-reflection symmetry of the discrete force.
+# For Q = S (cos 2theta, sin 2theta) depending on x only, H = -b Q + K Q'' with
+# b = A + C S^2, Q:H = -2 S^2 (b + 4 K theta'^2), and the stress divergence is
+#   F_x = d/dx [ -lam Hxx + 2 lam (Q:H) Qxx - 8 K S^2 theta'^2 - zeta c1 Qxx ]
+#   F_y = d/dx [ -lam Hxy + 2 lam (Q:H) Qxy - 4 K S^2 theta''   - zeta c1 Qxy ]
+# (the -8 K S^2 theta'^2 is the Ericksen term, the -4 K S^2 theta'' the
+# antisymmetric Q.H - H.Q part).
+# ---------------------------------------------------------------------------
+def _pattern_force_exact(N, m, a, S, p, c1):
+    x = np.arange(N)
+    k = 2 * np.pi * m / N
+    th = a * np.sin(k * x)
+    th1 = a * k * np.cos(k * x)
+    th2 = -a * k * k * np.sin(k * x)
+    c, s = np.cos(2 * th), np.sin(2 * th)
+    b = p["A_ldg"] + p["C_ldg"] * S * S
+    K, lam, zeta = p["K"], p["lam"], p["zeta"]
+    qxx, qxy = S * c, S * s
+    qxx2 = -2 * S * th2 * s - 4 * S * th1 ** 2 * c
+    qxy2 = 2 * S * th2 * c - 4 * S * th1 ** 2 * s
+    hxx, hxy = -b * qxx + K * qxx2, -b * qxy + K * qxy2
+    qh = -2 * S * S * (b + 4 * K * th1 ** 2)
+    sxx = -lam * hxx + 2 * lam * qh * qxx - 8 * K * S * S * th1 ** 2 - zeta * c1 * qxx
+    syx = -lam * hxy + 2 * lam * qh * qxy - 4 * K * S * S * th2 - zeta * c1 * qxy
+    kk = 2 * np.pi * np.fft.fftfreq(N) * 1j
+    dx = lambda g: np.real(np.fft.ifft(kk * np.fft.fft(g)))   # spectral d/dx
+    return (qxx, qxy), (dx(sxx), dx(syx))
+
+
+@pytest.mark.parametrize("lam,zeta,A0,gl", [(0.0, 0.0, 0.1, 3.0), (0.7, 0.0, 0.1, 6.0),
+                                           (2.0, 0.0, 0.1, 1.0), (0.7, 0.03, 0.1, 4.0)])
+def test_p18_nematic_force_of_director_pattern(lam, zeta, A0, gl):
+    phibar, S, a, m = 0.2, 0.3, 0.6, 2
+    errs = []
+    for N in (64, 128):
+        # K ~ N^2 keeps every term's share of the force fixed under refinement
+        p = base_params(N, 4, lam=lam, zeta=zeta, A0=A0, gamma_ldg=gl, K=0.04 * (N / 64) ** 2)
+        (qxx, qxy), (Fx, Fy) = _pattern_force_exact(N, m, a, S, p, (1 + phibar) / 2)
+        o = _fresh(p, np.full((4, N), phibar), np.tile(qxx, (4, 1)), np.tile(qxy, (4, 1)))
+        G = o.macroscopic()["G_a"]          # uniform phi: no capillary force
+        scale = max(np.abs(Fx).max(), np.abs(Fy).max())
+        errs.append(max(np.abs(G[0][0] - Fx).max(), np.abs(G[1][0] - Fy).max()) / scale)
+        np.testing.assert_allclose(G[:, 1:], np.repeat(G[:, :1], 3, axis=1), atol=1e-18)
+    assert errs[1] < 0.02 and 3.6 < errs[0] / errs[1] < 4.4, errs
+
+
+def test_p18b_force_reflection_symmetry():
+    # reflecting across the diagonal maps (Qxx, Qxy)(x, y) -> (-Qxx, Qxy)(y, x) and
+    # (Fx, Fy)(x, y) -> (Fy, Fx)(y, x); the discrete operators share that symmetry
+    n = 24
+    p = base_params(n, n, lam=0.7, zeta=0.02)
+    ic = initial_fields(n, n, seed=18, phi_mean=0.1, phi_noise=0.4, S0=0.3)
+    o1 = _fresh(p, ic["phi"], ic["qxx"], ic["qxy"])
+    o2 = _fresh(p, ic["phi"].T, -ic["qxx"].T, ic["qxy"].T)
+    G1, G2 = o1.macroscopic()["G_a"], o2.macroscopic()["G_a"]
+    np.testing.assert_allclose(G2[0], G1[1].T, atol=1e-17)
+    np.testing.assert_allclose(G2[1], G1[0].T, atol=1e-17)
+
+
+def test_p11c_director_turns_with_shear_wave_vorticity():
+    # u_x = U sin(k y), Q uniform, lam = K = A = C = zeta = 0: the only Q dynamics is
+    # co-rotation, so q = Qxx + i Qxy obeys q <- q (1 - 2 i w h) per sub-step with
+    # w = (d_y u_x - d_x u_y) / 2 = U sin(k) cos(k y) / 2 (central differences).
+    N, U, S, th0 = 32, 2e-2, 0.2, 0.4
+    p = base_params(4, N, lam=0.0, K=0.0, A0=0.0, zeta=0.0, gamma=0.0)
+    y = np.arange(N)[:, None] * np.ones((1, 4))
+    k = 2 * np.pi / N
+    ua = np.array([U * np.sin(k * y), 0 * y])
+    z = np.zeros((N, 4))
+    o = _fresh(p, z, z + S * np.cos(2 * th0), z + S * np.sin(2 * th0), u_a=ua, u_p=ua)
+    o.step(1)
+    w = U * np.sin(k) * np.cos(k * y) / 2
+    q = S * np.exp(2j * th0) * (1 - 2j * w / p["n_sub"]) ** p["n_sub"]
+    np.testing.assert_allclose(o.qxx + 1j * o.qxy, q, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P19: a right-moving acoustic wave travels at c_s = 1/sqrt(3) in +x
+# ---------------------------------------------------------------------------
+def test_p19_acoustic_wave_direction_and_speed():
+    N, eps, steps = 64, 1e-5, 32
+    p = base_params(N, 4, zeta=0.0, lam=0.0, gamma=0.0)
+    x = np.arange(N)[None, :] * np.ones((4, 1))
+    k = 2 * np.pi / N
+    cs = np.sqrt(1.0 / 3.0)
+    rho = 1.0 + eps * np.cos(k * x)
+    u = np.array([cs * eps * np.cos(k * x), 0 * x])
+    z = np.zeros((4, N))
+    o = _fresh(p, z, z, z)
+    o.f_a = O.equilibrium(rho, u)
+    o.f_p = O.equilibrium(rho, u)
+    o.step(steps)
+    for key in ("rho_a", "rho_p"):
+        r = o.get_fields()[key][0] - 1.0
+        phase = np.angle((r * np.exp(-1j * k * np.arange(N))).sum())
+        # LB sound is weakly dispersive (1.5% at this k); the wrong direction is 200% off
+        assert abs(-phase / (k * cs * steps) - 1.0) < 3e-2, (key, phase)

@@ -1,0 +1,165 @@
+"""Throughput of the coupled two-fluid active-nematic step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large_2048]
+
+Prints one JSON line: MLUPS (million lattice-site updates per second, one update
+= one coupled step of one site: both lattice-Boltzmann fluids plus all
+finite-difference sub-steps), the HBM roofline of the dominant kernel measured
+with HIP events on the solver's stream, and the FP64 oracle timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# Algorithmic bytes per lattice site moved by each kernel (float32 storage):
+# populations 2 fluids x 9 x 4 B read and written, phi/Qxx/Qxy 12 B, and the
+# frozen velocities (u_a, u_c: 16 B) that link the collision and sub-step kernels.
+ALG_BYTES = {
+    "step": 168,        # whole coupled step: 2*9*4*2 + 3*4*2
+    "collide": 172,     # pull+write populations (144), read phi/Q (12), write u_a, u_c (16)
+    "substep": 40,      # read phi/Q (12) and u_a/u_c (16), write phi/Q (12)
+}
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2511_00445_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
+def cpu_baseline(params, ic, budget_s: float):
+    """The FP64 oracle, unchanged, on the same grid: one coupled step (more if
+    the budget allows)."""
+    from oracle.tfan_oracle import Oracle
+    o = Oracle(params)
+    o.init_fields(ic["phi"], ic["qxx"], ic["qxy"])
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el * (steps + 1) / steps > budget_s:
+            break
+    sites = params["nx"] * params["ny"]
+    return {"value": sites * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} coupled step(s) of the full {params['nx']}x{params['ny']} grid, "
+                      f"numpy FP64 oracle, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="large_2048")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(a y-slab decomposition is described in the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2511_00445_amd import Sim
+    from paper_2511_00445_amd.workloads import WORKLOADS, initial_fields, workload_params
+
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    p = workload_params(args.workload)
+    nx, ny = p["nx"], p["ny"]
+    ic = initial_fields(nx, ny, seed=w["seeds"][0], phi_mean=w["phi_mean"])
+    sim = Sim(p, device="cuda:0")
+    sim.init_fields(**ic)
+    print(f"[bench] {args.workload}: {nx}x{ny}, warmup {args.warmup}", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    sim.sync()
+    launches_per_step = 1 + p["n_sub"]
+    sim.kernel_timing(args.steps * launches_per_step + 16)
+    stream = sim.stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    region_ms = ev0.elapsed_time(ev1)
+    ktimes = sim.kernel_times()
+    sim.kernel_timing(0)
+    diag = sim.diagnostics()
+    if diag["status"] != 0:
+        raise SystemExit(f"benchmark state is unhealthy: status {diag['status']}")
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    sites = nx * ny
+    mlups = sites * args.steps / wall / 1e6
+    # dominant kernel: largest total time in the timed region
+    name, (ms_tot, count) = max(((k, v) for k, v in ktimes.items() if v[1] > 0), key=lambda kv: kv[1][0])
+    avg_s = ms_tot / count / 1e3
+    alg = ALG_BYTES[name] * sites
+    achieved = alg / avg_s / 1e9
+    traffic = measured_traffic(name)
+    step_gbs = ALG_BYTES["step"] * sites * args.steps / wall / 1e9
+    out = {
+        "metric": "MLUPS per coupled step",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {nx}x{ny} periodic, plain float32 path, "
+                               f"zeta={p['zeta']}, n_sub={p['n_sub']}, seed {w['seeds'][0]}",
+                   "nx": nx, "ny": ny, "n_sub": p["n_sub"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2)},
+        "step_roofline": {"alg_bytes_per_site": ALG_BYTES["step"], "achieved": round(step_gbs, 1),
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "kernels_ms": {k: [round(v[0], 3), v[1]] for k, v in ktimes.items() if v[1] > 0},
+        "event_region_ms": round(region_ms, 3),
+        "source_hash": source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, ic, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

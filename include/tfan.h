@@ -1,0 +1,168 @@
+/*
+ * tfan.h -- C ABI of the MI355X (gfx950) solver for the two-fluid
+ * active-nematic mixture of arXiv 2511.00445 ("Phase separation dynamics and
+ * active turbulence in a binary fluid mixture").
+ *
+ * One coupled time step (Numerical Simulation section) advances, on a 2D
+ * periodic nx x ny lattice:
+ *   - two D2Q9 BGK lattice-Boltzmann fluids with Guo forcing: the active
+ *     fluid (velocity u_a, the paper's u1, Model Eq. 4) and the passive fluid
+ *     (u_p, the paper's u2, Model Eq. 5), coupled by the drag
+ *     F_drag = gamma c1 c2 (u_p - u_a);
+ *   - the active fluid feels the Beris-Edwards elastic stress (Model, elastic
+ *     stress display), the active stress -zeta c1 Q (Model, active force) and
+ *     the share c1 of the capillary force -phi grad(mu) (Model, capillary force);
+ *     the passive fluid feels the share c2 of the capillary force;
+ *   - n_sub forward-Euler finite-difference sub-steps (h = 1/n_sub) of the
+ *     Cahn-Hilliard equation for phi (Model, Eqs. 1-3) and of the Beris-Edwards
+ *     equation for Q (Model, Eqs. 11-12), with u_a and u_c = c1 u_a + c2 u_p
+ *     frozen at their start-of-step values.
+ * Lattice units (dx = dt = 1).  phi in [-1, 1] is the composition order
+ * parameter; c1 = (1 + phi)/2 and c2 = (1 - phi)/2 are the active and passive
+ * fractions.  Q is symmetric and traceless, stored as (Qxx, Qxy).
+ *
+ * Arrays: every field is row-major [ny][nx] with x fastest; vector fields are
+ * two such planes, x component first ([2][ny][nx]).  Host arrays are float64.
+ *
+ * Ownership: the caller owns every host array and the device workspace
+ * (device memory of tfan_workspace_bytes() bytes, 256-byte aligned).  The
+ * library never allocates device memory and never frees caller memory; it owns
+ * only the opaque handle, released by tfan_destroy().  A handle is bound to one
+ * HIP stream and one device; it is not thread-safe.
+ *
+ * Errors: every int-returning function returns TFAN_OK (0) or a negative
+ * tfan_status; tfan_last_error() gives the message.  Launch errors are reported
+ * by the launching call; errors during kernel execution surface at the next
+ * synchronising call (get_fields, diagnostics, get_state, sync).
+ */
+#ifndef TFAN_H
+#define TFAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tfan_status {
+  TFAN_OK = 0,
+  TFAN_EINVAL = -1,     /* bad parameter, size or NULL pointer                 */
+  TFAN_ENOMEM = -2,     /* workspace or host buffer too small                  */
+  TFAN_EHIP = -3,       /* HIP runtime or launch error (message kept)           */
+  TFAN_ENONFINITE = -4, /* diagnostics found NaN/Inf in the state               */
+  TFAN_EUNSTABLE = -5   /* diagnostics found max |u| above 0.3 (Mach guard)     */
+} tfan_status;
+
+/* Population storage format. */
+enum { TFAN_STORAGE_F32 = 0 };
+
+/* Problem statement (Model and Numerical Simulation sections).  Limits:
+ * 8 <= nx, ny <= 32768, nx*ny <= 2^28, tau > 1/2, 1 <= n_sub <= 64, all reals
+ * finite, rho0 > 0, M >= 0, K >= 0, Gamma >= 0, gamma >= 0, kappa >= 0. */
+typedef struct tfan_params {
+  int32_t nx, ny;      /* periodic grid                                          */
+  int32_t n_sub;       /* finite-difference sub-steps per lattice-Boltzmann step */
+  int32_t storage;     /* TFAN_STORAGE_F32                                       */
+  double rho0;         /* density of each fluid (rho_1 = rho_2)                  */
+  double tau_a, tau_p; /* BGK relaxation times; viscosity (tau - 1/2)/3          */
+  double gamma;        /* inter-fluid drag coefficient                           */
+  double A_ch, kappa;  /* mu = A_ch (phi^3 - phi) - kappa lap(phi)               */
+  double M;            /* Cahn-Hilliard mobility                                 */
+  double A_ldg, C_ldg; /* Landau-de Gennes (A/2) TrQ^2 + (C/4) TrQ^4 (Model Eq. 8) */
+  double K;            /* Frank elastic constant                                 */
+  double lam;          /* tumbling parameter lambda                              */
+  double Gamma;        /* rotational diffusion constant                          */
+  double zeta;         /* activity, > 0 extensile                                */
+} tfan_params;
+
+/* Diagnostics: sums over all sites, accumulated in float64 on the device from
+ * the float32 state (Results section observables). */
+typedef struct tfan_diag {
+  int64_t step;        /* coupled steps taken since init_fields / set_state      */
+  int64_t nonfinite;   /* NaN/Inf count over phi, Q and both population sets     */
+  double phi_sum;      /* sum phi                                                */
+  double phi_sq_sum;   /* sum phi^2 (std. deviation Delta of phi)                */
+  double mass_a;       /* sum rho_a                                              */
+  double mass_p;       /* sum rho_p                                              */
+  double ke_a;         /* 1/2 sum rho_a |u_a|^2                                   */
+  double ke_p;         /* 1/2 sum rho_p |u_p|^2                                   */
+  double ke_c;         /* 1/2 sum |u_c|^2  (u_c = c1 u_a + c2 u_p)                */
+  double ua_sq;        /* sum |u_a|^2                                            */
+  double uc_sq;        /* sum |u_c|^2                                            */
+  double enstrophy_a;  /* sum omega_a^2, omega = d_x u_y - d_y u_x                */
+  double enstrophy_c;  /* sum omega_c^2                                          */
+  double elastic;      /* sum (K/2) |grad Q|^2, |grad Q|^2 = sum_kij (d_k Q_ij)^2 */
+  double s_sum;        /* sum S, S = sqrt(Qxx^2 + Qxy^2)                          */
+  double umax;         /* max over sites of max(|u_a|, |u_p|)                    */
+} tfan_diag;
+
+typedef struct tfan_sim tfan_sim;
+
+/* Host-only validation of a parameter block; no GPU call. */
+int tfan_check_params(const tfan_params* p);
+
+/* Device workspace needed for p (0 if p is invalid); no GPU call. */
+size_t tfan_workspace_bytes(const tfan_params* p);
+
+/* Bind a solver to the caller's device workspace (on the current HIP device)
+ * and stream (hipStream_t, NULL = default stream).  *out receives the handle.
+ * TFAN_EINVAL for bad parameters, TFAN_ENOMEM if bytes is too small. */
+int tfan_create(const tfan_params* p, void* dev_workspace, size_t bytes,
+                void* hip_stream, tfan_sim** out);
+
+/* Set the state at step 0: phi, qxx, qxy [ny][nx]; u_a, u_p [2][ny][nx] or
+ * NULL for zero.  Both population sets start at the D2Q9 equilibrium at
+ * density rho0 and the given velocity.  Synchronises the stream. */
+int tfan_init_fields(tfan_sim* s, const double* phi, const double* qxx,
+                     const double* qxy, const double* u_a, const double* u_p);
+
+/* Enqueue n >= 0 coupled steps on the handle's stream; returns without
+ * waiting. */
+int tfan_step(tfan_sim* s, int64_t n);
+
+/* Copy the current fields to host float64 arrays (any may be NULL):
+ * phi, qxx, qxy, rho_a, rho_p [ny][nx]; u_a, u_p [2][ny][nx].  The velocities
+ * are the half-force-corrected ones of the step's own velocity solve.
+ * Synchronises the stream. */
+int tfan_get_fields(tfan_sim* s, double* phi, double* qxx, double* qxy,
+                    double* u_a, double* u_p, double* rho_a, double* rho_p);
+
+/* Fill *out.  Returns TFAN_OK, or TFAN_ENONFINITE / TFAN_EUNSTABLE (with *out
+ * still filled) when the state is broken.  Synchronises the stream. */
+int tfan_diagnostics(tfan_sim* s, tfan_diag* out);
+
+/* Checkpoint: the raw device state (populations, phi, Q, step counter).
+ * tfan_state_bytes() gives the size; set_state restores it bit for bit. */
+size_t tfan_state_bytes(const tfan_sim* s);
+int tfan_get_state(tfan_sim* s, void* host, size_t bytes);
+int tfan_set_state(tfan_sim* s, const void* host, size_t bytes);
+
+/* Wait for the handle's stream; reports execution errors. */
+int tfan_sync(tfan_sim* s);
+
+/* Steps taken so far. */
+int64_t tfan_step_count(const tfan_sim* s);
+
+/* Kernel timing with HIP events on the handle's stream.  enable(cap) starts
+ * recording up to cap launches (cap = 0 stops and frees the events);
+ * tfan_kernel_times() synchronises, then fills ms_total[k] and launches[k] for
+ * the first n kernel ids (k < tfan_kernel_count()).  Recording stops silently
+ * once cap launches were recorded. */
+int tfan_kernel_timing(tfan_sim* s, int64_t cap);
+int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n);
+int tfan_kernel_count(void);
+const char* tfan_kernel_name(int id);
+
+/* Release the handle (never the workspace). NULL is ignored. */
+void tfan_destroy(tfan_sim* s);
+
+/* Message of the last failure on s; s = NULL gives the last failure of a call
+ * without a valid handle (check_params, create). */
+const char* tfan_last_error(const tfan_sim* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFAN_H */

@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libtfan.so (include/tfan.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies the device workspace and the stream.  There is no CPU
+fallback: without the built library or a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtfan.so")
+
+TFAN_OK, TFAN_EINVAL, TFAN_ENOMEM, TFAN_EHIP, TFAN_ENONFINITE, TFAN_EUNSTABLE = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "TFAN_OK", -1: "TFAN_EINVAL", -2: "TFAN_ENOMEM", -3: "TFAN_EHIP",
+                -4: "TFAN_ENONFINITE", -5: "TFAN_EUNSTABLE"}
+TFAN_STORAGE_F32 = 0
+
+
+class tfan_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_sub", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("rho0", ctypes.c_double), ("tau_a", ctypes.c_double),
+                ("tau_p", ctypes.c_double), ("gamma", ctypes.c_double), ("A_ch", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("M", ctypes.c_double), ("A_ldg", ctypes.c_double),
+                ("C_ldg", ctypes.c_double), ("K", ctypes.c_double), ("lam", ctypes.c_double),
+                ("Gamma", ctypes.c_double), ("zeta", ctypes.c_double)]
+
+
+class tfan_diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64)] + [
+        (k, ctypes.c_double) for k in ("phi_sum", "phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p",
+                                       "ke_c", "ua_sq", "uc_sq", "enstrophy_a", "enstrophy_c",
+                                       "elastic", "s_sum", "umax")]
+
+
+class TfanError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_dp = _P(ctypes.c_double)
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtfan.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2511_00445_amd.build`")
+    lib = ctypes.CDLL(path)
+    sigs = {
+        "tfan_check_params": (ctypes.c_int, [_P(tfan_params)]),
+        "tfan_workspace_bytes": (ctypes.c_size_t, [_P(tfan_params)]),
+        "tfan_create": (ctypes.c_int, [_P(tfan_params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+        "tfan_init_fields": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp]),
+        "tfan_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "tfan_get_fields": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "tfan_diagnostics": (ctypes.c_int, [_vp, _P(tfan_diag)]),
+        "tfan_state_bytes": (ctypes.c_size_t, [_vp]),
+        "tfan_get_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+        "tfan_set_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+        "tfan_sync": (ctypes.c_int, [_vp]),
+        "tfan_step_count": (ctypes.c_int64, [_vp]),
+        "tfan_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "tfan_kernel_times": (ctypes.c_int, [_vp, _dp, _P(ctypes.c_int64), ctypes.c_int]),
+        "tfan_kernel_count": (ctypes.c_int, []),
+        "tfan_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
+        "tfan_destroy": (None, [_vp]),
+        "tfan_last_error": (ctypes.c_char_p, [_vp]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def make_params(p: dict) -> tfan_params:
+    out = tfan_params()
+    for name, typ in tfan_params._fields_:
+        if name == "storage":
+            out.storage = int(p.get("storage", TFAN_STORAGE_F32))
+        else:
+            setattr(out, name, int(p[name]) if typ is ctypes.c_int32 else float(p[name]))
+    return out
+
+
+def check_params(p: dict) -> None:
+    """Host-only validation (no GPU call); raises TfanError."""
+    lib = load_library()
+    rc = lib.tfan_check_params(ctypes.byref(make_params(p)))
+    if rc != TFAN_OK:
+        raise TfanError(rc, lib.tfan_last_error(None).decode())
+
+
+def workspace_bytes(p: dict) -> int:
+    return int(load_library().tfan_workspace_bytes(ctypes.byref(make_params(p))))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+class Sim:
+    """One solver on one device and stream; the device workspace is a torch tensor."""
+
+    def __init__(self, params: dict, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the solver runs only on the GPU")
+        self.lib = load_library()
+        self.params = dict(params)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        cp = make_params(params)
+        rc = self.lib.tfan_check_params(ctypes.byref(cp))
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_last_error(None).decode())
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        nbytes = int(self.lib.tfan_workspace_bytes(ctypes.byref(cp)))
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._handle = _vp()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tfan_create(ctypes.byref(cp), _vp(aligned), nbytes, _vp(self.stream.cuda_stream),
+                                      ctypes.byref(self._handle))
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_last_error(None).decode())
+
+    # -- helpers -----------------------------------------------------------------
+    def _check(self, rc):
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_last_error(self._handle).decode())
+
+    @property
+    def handle(self):
+        return self._handle
+
+    # -- the ABI -------------------------------------------------------------------
+    def init_fields(self, phi, qxx, qxy, u_a=None, u_p=None):
+        s = (self.ny, self.nx)
+        arrs = [_f64(phi, s), _f64(qxx, s), _f64(qxy, s), _f64(u_a, (2,) + s), _f64(u_p, (2,) + s)]
+        self._check(self.lib.tfan_init_fields(self._handle, *[_ptr(a) for a in arrs]))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.tfan_step(self._handle, int(n)))
+
+    def get_fields(self) -> dict:
+        s = (self.ny, self.nx)
+        out = dict(phi=np.empty(s), qxx=np.empty(s), qxy=np.empty(s), u_a=np.empty((2,) + s),
+                   u_p=np.empty((2,) + s), rho_a=np.empty(s), rho_p=np.empty(s))
+        self._check(self.lib.tfan_get_fields(self._handle, *[_ptr(out[k]) for k in
+                                                             ("phi", "qxx", "qxy", "u_a", "u_p", "rho_a", "rho_p")]))
+        return out
+
+    def diagnostics(self) -> dict:
+        """Diagnostics sums; 'status' is TFAN_OK, TFAN_ENONFINITE or TFAN_EUNSTABLE."""
+        d = tfan_diag()
+        rc = self.lib.tfan_diagnostics(self._handle, ctypes.byref(d))
+        if rc not in (TFAN_OK, TFAN_ENONFINITE, TFAN_EUNSTABLE):
+            self._check(rc)
+        out = {name: getattr(d, name) for name, _ in tfan_diag._fields_}
+        out["status"] = rc
+        return out
+
+    def state_bytes(self) -> int:
+        return int(self.lib.tfan_state_bytes(self._handle))
+
+    def get_state(self) -> np.ndarray:
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        self._check(self.lib.tfan_get_state(self._handle, buf.ctypes.data_as(_vp), buf.size))
+        return buf
+
+    def set_state(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.tfan_set_state(self._handle, buf.ctypes.data_as(_vp), buf.size))
+
+    def sync(self):
+        self._check(self.lib.tfan_sync(self._handle))
+
+    def step_count(self) -> int:
+        return int(self.lib.tfan_step_count(self._handle))
+
+    def kernel_timing(self, cap: int):
+        self._check(self.lib.tfan_kernel_timing(self._handle, int(cap)))
+
+    def kernel_times(self) -> dict:
+        k = int(self.lib.tfan_kernel_count())
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int64 * k)()
+        self._check(self.lib.tfan_kernel_times(self._handle, ms, cnt, k))
+        return {self.lib.tfan_kernel_name(i).decode(): (ms[i], cnt[i]) for i in range(k)}
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self.lib.tfan_destroy(self._handle)
+            self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

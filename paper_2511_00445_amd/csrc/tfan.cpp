@@ -1,0 +1,463 @@
+// Host side of the C ABI declared in include/tfan.h: parameter validation,
+// workspace layout, kernel launches, host<->device conversion, checkpoints and
+// event-based kernel timing.
+#include "tfan.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tfan_internal.h"
+
+using tfan::DevParams;
+using tfan::DevState;
+
+struct tfan_sim {
+  tfan_params p{};
+  DevParams dp{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // workspace carve-up
+  float* f[2] = {nullptr, nullptr};    // [18][n] each
+  float* phi[2] = {nullptr, nullptr};  // [n]
+  float* q[2] = {nullptr, nullptr};    // [2][n]
+  float* U = nullptr;                  // [4][n]: u_a, u_c of the current step
+  float* aux = nullptr;                // [7][n]: fields / staging
+  double* partials = nullptr;          // [diag blocks][kDiagSlots]
+  double* result = nullptr;            // [kDiagSlots]
+  int cur = 0;                         // index of the buffers holding the state
+  int64_t step = 0;
+  std::string err;
+  // kernel timing
+  std::vector<hipEvent_t> ev;          // 2 per recorded launch
+  std::vector<int> ev_kernel;
+  int64_t ev_cap = 0, ev_used = 0;
+  double ms_total[tfan::K_COUNT] = {};
+  int64_t launches[tfan::K_COUNT] = {};
+};
+
+namespace {
+
+std::string g_err;  // failures without a handle
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int fail(tfan_sim* s, int code, const std::string& msg) {
+  if (s) s->err = msg; else g_err = msg;
+  return code;
+}
+
+int hip_fail(tfan_sim* s, hipError_t e, const char* where) {
+  return fail(s, TFAN_EHIP, std::string(where) + ": " + hipGetErrorName(e) + " (" +
+                                hipGetErrorString(e) + ")");
+}
+
+std::string check(const tfan_params* p) {
+  if (!p) return "params is NULL";
+  if (p->nx < 8 || p->ny < 8 || p->nx > 32768 || p->ny > 32768) return "nx, ny must be in [8, 32768]";
+  if ((int64_t)p->nx * p->ny > (int64_t(1) << 28)) return "nx * ny must not exceed 2^28";
+  if (p->n_sub < 1 || p->n_sub > 64) return "n_sub must be in [1, 64]";
+  if (p->storage != TFAN_STORAGE_F32) return "unsupported storage format";
+  const double r[] = {p->rho0, p->tau_a, p->tau_p, p->gamma, p->A_ch, p->kappa, p->M,
+                      p->A_ldg, p->C_ldg, p->K, p->lam, p->Gamma, p->zeta};
+  for (double v : r)
+    if (!std::isfinite(v)) return "parameters must be finite";
+  if (!(p->rho0 > 0)) return "rho0 must be positive";
+  if (!(p->tau_a > 0.5) || !(p->tau_p > 0.5)) return "tau_a and tau_p must exceed 1/2";
+  if (p->gamma < 0 || p->kappa < 0 || p->M < 0 || p->K < 0 || p->Gamma < 0)
+    return "gamma, kappa, M, K and Gamma must be non-negative";
+  return "";
+}
+
+struct Layout {
+  size_t f[2], phi[2], q[2], U, aux, partials, result, total;
+};
+
+Layout layout(const tfan_params* p) {
+  const size_t n = (size_t)p->nx * p->ny;
+  DevParams dp{};
+  dp.n = (int)n;
+  const size_t nb = (size_t)tfan::diag_blocks(dp);
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  for (int k = 0; k < 2; ++k) L.f[k] = take(18 * n * sizeof(float));
+  for (int k = 0; k < 2; ++k) L.phi[k] = take(n * sizeof(float));
+  for (int k = 0; k < 2; ++k) L.q[k] = take(2 * n * sizeof(float));
+  L.U = take(4 * n * sizeof(float));
+  L.aux = take(7 * n * sizeof(float));
+  L.partials = take(nb * tfan::kDiagSlots * sizeof(double));
+  L.result = take(tfan::kDiagSlots * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+DevParams dev_params(const tfan_params* p) {
+  DevParams d{};
+  d.nx = p->nx;
+  d.ny = p->ny;
+  d.n = p->nx * p->ny;
+  d.n_sub = p->n_sub;
+  d.rho0 = (float)p->rho0;
+  d.om_a = (float)(1.0 / p->tau_a);
+  d.om_p = (float)(1.0 / p->tau_p);
+  d.gk_a = (float)(1.0 - 0.5 / p->tau_a);
+  d.gk_p = (float)(1.0 - 0.5 / p->tau_p);
+  d.gamma = (float)p->gamma;
+  d.A_ch = (float)p->A_ch;
+  d.kappa = (float)p->kappa;
+  d.M = (float)p->M;
+  d.A_ldg = (float)p->A_ldg;
+  d.halfC = (float)(0.5 * p->C_ldg);
+  d.K = (float)p->K;
+  d.lam = (float)p->lam;
+  d.Gamma = (float)p->Gamma;
+  d.zeta = (float)p->zeta;
+  d.h = (float)(1.0 / p->n_sub);
+  d.rho0_d = p->rho0;
+  return d;
+}
+
+DevState state_of(tfan_sim* s, int k) { return DevState{s->f[k], s->phi[k], s->q[k]}; }
+
+// Event bracketing of one launch when timing is on.
+struct TimedLaunch {
+  tfan_sim* s;
+  int kernel;
+  int64_t slot = -1;
+  TimedLaunch(tfan_sim* s_, int k) : s(s_), kernel(k) {
+    if (s->ev_used < s->ev_cap) {
+      slot = s->ev_used++;
+      s->ev_kernel[slot] = kernel;
+      (void)hipEventRecord(s->ev[2 * slot], s->stream);
+    }
+  }
+  ~TimedLaunch() {
+    if (slot >= 0) (void)hipEventRecord(s->ev[2 * slot + 1], s->stream);
+  }
+};
+
+void harvest(tfan_sim* s) {
+  for (int64_t k = 0; k < s->ev_used; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, s->ev[2 * k], s->ev[2 * k + 1]) == hipSuccess) {
+      s->ms_total[s->ev_kernel[k]] += ms;
+      s->launches[s->ev_kernel[k]] += 1;
+    }
+  }
+  s->ev_used = 0;
+}
+
+void free_events(tfan_sim* s) {
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  s->ev.clear();
+  s->ev_kernel.clear();
+  s->ev_cap = s->ev_used = 0;
+}
+
+int sync_stream(tfan_sim* s, const char* where) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, where);
+  return TFAN_OK;
+}
+
+// Host float64 -> device float32 through a pinned-free staging copy.
+int upload(tfan_sim* s, float* dst, const double* src, size_t count, std::vector<float>& tmp) {
+  tmp.resize(count);
+  for (size_t i = 0; i < count; ++i) tmp[i] = (float)src[i];
+  hipError_t e = hipMemcpyAsync(dst, tmp.data(), count * sizeof(float), hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "upload");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "upload");
+  return TFAN_OK;
+}
+
+int download(tfan_sim* s, double* dst, const float* src, size_t count, std::vector<float>& tmp,
+             double offset = 0.0) {
+  tmp.resize(count);
+  hipError_t e = hipMemcpyAsync(tmp.data(), src, count * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "download");
+  e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "download");
+  for (size_t i = 0; i < count; ++i) dst[i] = offset + (double)tmp[i];
+  return TFAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfan_check_params(const tfan_params* p) {
+  const std::string m = check(p);
+  return m.empty() ? TFAN_OK : fail(nullptr, TFAN_EINVAL, m);
+}
+
+size_t tfan_workspace_bytes(const tfan_params* p) {
+  if (!check(p).empty()) return 0;
+  return layout(p).total;
+}
+
+int tfan_create(const tfan_params* p, void* ws, size_t bytes, void* stream, tfan_sim** out) {
+  if (!out) return fail(nullptr, TFAN_EINVAL, "out is NULL");
+  *out = nullptr;
+  const std::string m = check(p);
+  if (!m.empty()) return fail(nullptr, TFAN_EINVAL, m);
+  if (!ws) return fail(nullptr, TFAN_EINVAL, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(nullptr, TFAN_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = layout(p);
+  if (bytes < L.total)
+    return fail(nullptr, TFAN_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  tfan_sim* s = new tfan_sim();
+  s->p = *p;
+  s->dp = dev_params(p);
+  s->stream = (hipStream_t)stream;
+  (void)hipGetDevice(&s->device);
+  char* base = (char*)ws;
+  for (int k = 0; k < 2; ++k) {
+    s->f[k] = (float*)(base + L.f[k]);
+    s->phi[k] = (float*)(base + L.phi[k]);
+    s->q[k] = (float*)(base + L.q[k]);
+  }
+  s->U = (float*)(base + L.U);
+  s->aux = (float*)(base + L.aux);
+  s->partials = (double*)(base + L.partials);
+  s->result = (double*)(base + L.result);
+  *out = s;
+  return TFAN_OK;
+}
+
+int tfan_init_fields(tfan_sim* s, const double* phi, const double* qxx, const double* qxy,
+                     const double* u_a, const double* u_p) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!phi || !qxx || !qxy) return fail(s, TFAN_EINVAL, "phi, qxx and qxy are required");
+  const size_t n = (size_t)s->dp.n;
+  for (const double* a : {phi, qxx, qxy})
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(a[i])) return fail(s, TFAN_EINVAL, "initial fields must be finite");
+  for (const double* a : {u_a, u_p})
+    if (a)
+      for (size_t i = 0; i < 2 * n; ++i)
+        if (!std::isfinite(a[i])) return fail(s, TFAN_EINVAL, "initial velocities must be finite");
+  std::vector<float> tmp;
+  s->cur = 0;
+  int rc;
+  if ((rc = upload(s, s->phi[0], phi, n, tmp))) return rc;
+  if ((rc = upload(s, s->q[0], qxx, n, tmp))) return rc;
+  if ((rc = upload(s, s->q[0] + n, qxy, n, tmp))) return rc;
+  std::vector<double> zero;
+  if (!u_a || !u_p) zero.assign(2 * n, 0.0);
+  if ((rc = upload(s, s->aux, u_a ? u_a : zero.data(), 2 * n, tmp))) return rc;
+  if ((rc = upload(s, s->aux + 2 * n, u_p ? u_p : zero.data(), 2 * n, tmp))) return rc;
+  {
+    TimedLaunch t(s, tfan::K_INIT);
+    hipError_t e = tfan::launch_init(s->dp, s->aux, state_of(s, 0), s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "init kernel launch");
+  }
+  s->step = 0;
+  return sync_stream(s, "init_fields");
+}
+
+int tfan_step(tfan_sim* s, int64_t nsteps) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(s, TFAN_EINVAL, "step count must be >= 0");
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int a = s->cur, b = 1 - s->cur;
+    {
+      TimedLaunch t(s, tfan::K_COLLIDE);
+      hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "collide kernel launch");
+    }
+    // sub-steps alternate the phi/Q buffers; the collide above already read state a
+    int src = a;
+    for (int m = 0; m < s->dp.n_sub; ++m) {
+      TimedLaunch t(s, tfan::K_FD);
+      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
+      src = 1 - src;
+    }
+    // the new state: populations in b, fields in src; keep them under one index
+    if (src != b) {
+      hipError_t e = hipMemcpyAsync(s->phi[b], s->phi[src], (size_t)s->dp.n * sizeof(float),
+                                    hipMemcpyDeviceToDevice, s->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->q[b], s->q[src], (size_t)2 * s->dp.n * sizeof(float),
+                           hipMemcpyDeviceToDevice, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "field copy");
+    }
+    s->cur = b;
+    s->step += 1;
+  }
+  return TFAN_OK;
+}
+
+int tfan_get_fields(tfan_sim* s, double* phi, double* qxx, double* qxy, double* u_a, double* u_p,
+                    double* rho_a, double* rho_p) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  const size_t n = (size_t)s->dp.n;
+  std::vector<float> tmp;
+  int rc;
+  if (u_a || u_p || rho_a || rho_p) {
+    TimedLaunch t(s, tfan::K_FIELDS);
+    hipError_t e = tfan::launch_fields(s->dp, state_of(s, s->cur), s->aux, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "fields kernel launch");
+  }
+  if (phi && (rc = download(s, phi, s->phi[s->cur], n, tmp))) return rc;
+  if (qxx && (rc = download(s, qxx, s->q[s->cur], n, tmp))) return rc;
+  if (qxy && (rc = download(s, qxy, s->q[s->cur] + n, n, tmp))) return rc;
+  if (rho_a && (rc = download(s, rho_a, s->aux, n, tmp, s->p.rho0))) return rc;
+  if (rho_p && (rc = download(s, rho_p, s->aux + n, n, tmp, s->p.rho0))) return rc;
+  if (u_a && (rc = download(s, u_a, s->aux + 2 * n, 2 * n, tmp))) return rc;
+  if (u_p && (rc = download(s, u_p, s->aux + 4 * n, 2 * n, tmp))) return rc;
+  return sync_stream(s, "get_fields");
+}
+
+int tfan_diagnostics(tfan_sim* s, tfan_diag* out) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!out) return fail(s, TFAN_EINVAL, "out is NULL");
+  {
+    TimedLaunch t(s, tfan::K_FIELDS);
+    hipError_t e = tfan::launch_fields(s->dp, state_of(s, s->cur), s->aux, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "fields kernel launch");
+  }
+  {
+    TimedLaunch t(s, tfan::K_DIAG);
+    hipError_t e = tfan::launch_diag(s->dp, state_of(s, s->cur), s->aux, s->partials,
+                                     tfan::diag_blocks(s->dp), s->result, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "diagnostics kernel launch");
+  }
+  double r[tfan::kDiagSlots];
+  hipError_t e = hipMemcpyAsync(r, s->result, sizeof(r), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "diagnostics copy");
+  int rc = sync_stream(s, "diagnostics");
+  if (rc) return rc;
+  out->step = s->step;
+  out->nonfinite = (int64_t)r[tfan::D_NONFINITE];
+  out->phi_sum = r[tfan::D_PHI];
+  out->phi_sq_sum = r[tfan::D_PHI2];
+  out->mass_a = r[tfan::D_MASS_A];
+  out->mass_p = r[tfan::D_MASS_P];
+  out->ke_a = r[tfan::D_KE_A];
+  out->ke_p = r[tfan::D_KE_P];
+  out->ke_c = r[tfan::D_KE_C];
+  out->ua_sq = r[tfan::D_UA2];
+  out->uc_sq = r[tfan::D_UC2];
+  out->enstrophy_a = r[tfan::D_ENS_A];
+  out->enstrophy_c = r[tfan::D_ENS_C];
+  out->elastic = r[tfan::D_ELASTIC];
+  out->s_sum = r[tfan::D_S];
+  out->umax = r[tfan::D_UMAX];
+  if (out->nonfinite > 0) return fail(s, TFAN_ENONFINITE, "state holds non-finite values");
+  if (out->umax > 0.3) return fail(s, TFAN_EUNSTABLE, "max |u| exceeds 0.3");
+  return TFAN_OK;
+}
+
+size_t tfan_state_bytes(const tfan_sim* s) {
+  if (!s) return 0;
+  return sizeof(int64_t) + (size_t)s->dp.n * 21 * sizeof(float);
+}
+
+int tfan_get_state(tfan_sim* s, void* host, size_t bytes) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!host) return fail(s, TFAN_EINVAL, "host buffer is NULL");
+  if (bytes < tfan_state_bytes(s)) return fail(s, TFAN_ENOMEM, "host buffer too small");
+  const size_t n = (size_t)s->dp.n;
+  char* h = (char*)host;
+  std::memcpy(h, &s->step, sizeof(int64_t));
+  h += sizeof(int64_t);
+  hipError_t e = hipMemcpyAsync(h, s->f[s->cur], 18 * n * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h + 18 * n * sizeof(float), s->phi[s->cur], n * sizeof(float),
+                       hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h + 19 * n * sizeof(float), s->q[s->cur], 2 * n * sizeof(float),
+                       hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "get_state");
+  return sync_stream(s, "get_state");
+}
+
+int tfan_set_state(tfan_sim* s, const void* host, size_t bytes) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!host) return fail(s, TFAN_EINVAL, "host buffer is NULL");
+  if (bytes != tfan_state_bytes(s)) return fail(s, TFAN_EINVAL, "state size does not match this grid");
+  const size_t n = (size_t)s->dp.n;
+  const char* h = (const char*)host;
+  int64_t step;
+  std::memcpy(&step, h, sizeof(int64_t));
+  if (step < 0) return fail(s, TFAN_EINVAL, "negative step counter in state");
+  h += sizeof(int64_t);
+  s->cur = 0;
+  hipError_t e = hipMemcpyAsync(s->f[0], h, 18 * n * sizeof(float), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->phi[0], h + 18 * n * sizeof(float), n * sizeof(float), hipMemcpyHostToDevice,
+                       s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->q[0], h + 19 * n * sizeof(float), 2 * n * sizeof(float),
+                       hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "set_state");
+  s->step = step;
+  return sync_stream(s, "set_state");
+}
+
+int tfan_sync(tfan_sim* s) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  return sync_stream(s, "sync");
+}
+
+int64_t tfan_step_count(const tfan_sim* s) { return s ? s->step : -1; }
+
+int tfan_kernel_timing(tfan_sim* s, int64_t cap) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (cap < 0 || cap > (int64_t(1) << 20)) return fail(s, TFAN_EINVAL, "cap must be in [0, 2^20]");
+  int rc = sync_stream(s, "kernel_timing");
+  if (rc) return rc;
+  free_events(s);
+  for (int k = 0; k < tfan::K_COUNT; ++k) { s->ms_total[k] = 0; s->launches[k] = 0; }
+  if (cap == 0) return TFAN_OK;
+  s->ev.resize(2 * cap);
+  s->ev_kernel.resize(cap);
+  for (size_t i = 0; i < s->ev.size(); ++i) {
+    hipError_t e = hipEventCreate(&s->ev[i]);
+    if (e != hipSuccess) {
+      s->ev.resize(i);
+      free_events(s);
+      return hip_fail(s, e, "hipEventCreate");
+    }
+  }
+  s->ev_cap = cap;
+  return TFAN_OK;
+}
+
+int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (n < 0 || n > tfan::K_COUNT || (n > 0 && (!ms_total || !launches)))
+    return fail(s, TFAN_EINVAL, "bad output arrays");
+  int rc = sync_stream(s, "kernel_times");
+  if (rc) return rc;
+  harvest(s);
+  for (int k = 0; k < n; ++k) {
+    ms_total[k] = s->ms_total[k];
+    launches[k] = s->launches[k];
+  }
+  return TFAN_OK;
+}
+
+int tfan_kernel_count(void) { return tfan::K_COUNT; }
+
+const char* tfan_kernel_name(int id) {
+  static const char* names[tfan::K_COUNT] = {"collide", "substep", "init", "fields", "diagnostics"};
+  return (id >= 0 && id < tfan::K_COUNT) ? names[id] : "";
+}
+
+void tfan_destroy(tfan_sim* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  free_events(s);
+  delete s;
+}
+
+const char* tfan_last_error(const tfan_sim* s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Internal declarations shared by the host library (tfan.cpp) and the gfx950
+// kernels (tfan_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace tfan {
+
+// Parameters in the form the kernels use (float32 arithmetic).
+struct DevParams {
+  int nx, ny;          // grid
+  int n;               // nx * ny
+  int n_sub;           // sub-steps per step
+  float rho0;
+  float om_a, om_p;    // 1/tau
+  float gk_a, gk_p;    // Guo prefactor 1 - 1/(2 tau)
+  float gamma;         // drag
+  float A_ch, kappa, M;
+  float A_ldg, halfC;  // H_bulk = -(A + (C/2) TrQ^2) Q
+  float K, lam, Gamma, zeta;
+  float h;             // 1 / n_sub
+  double rho0_d;       // rho0 for float64 reductions
+};
+
+// Number of float64 slots in one diagnostics record.
+constexpr int kDiagSlots = 16;
+// Slot order of the diagnostics record (the last is a maximum, the rest sums).
+enum DiagSlot {
+  D_PHI = 0, D_PHI2, D_MASS_A, D_MASS_P, D_KE_A, D_KE_P, D_KE_C, D_UA2, D_UC2,
+  D_ENS_A, D_ENS_C, D_ELASTIC, D_S, D_NONFINITE, D_UNUSED, D_UMAX
+};
+
+// Device buffers of one solver (all float32, each [ny][nx] plane n floats).
+struct DevState {
+  float* f;        // populations, shifted by -w_i rho0: [2 fluids][9][n]
+  float* phi;      // [n]
+  float* q;        // [2][n] (Qxx, Qxy)
+};
+
+// Kernel ids for timing.
+enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_COUNT };
+
+// Launchers (return hipGetLastError() after the launch).
+hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
+                       hipStream_t st);
+hipError_t launch_collide(const DevParams& P, DevState in, float* f_out, float* u_out /*[4][n]*/,
+                          hipStream_t st);
+hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
+                     hipStream_t st);
+hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: drho_a, drho_p, u_a, u_p*/,
+                         hipStream_t st);
+hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,
+                       double* partials, int nblocks, double* result, hipStream_t st);
+int diag_blocks(const DevParams& P);
+
+}  // namespace tfan

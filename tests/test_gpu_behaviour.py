@@ -1,0 +1,146 @@
+"""GPU behaviour through the C ABI: error codes, health flags, determinism,
+checkpoint round trip, and closed-form pins re-run on the float32 path."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2511_00445_amd.workloads import base_params, initial_fields, workload_params
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make(p, ic=None, **kw):
+    from paper_2511_00445_amd import Sim
+    s = Sim(p)
+    ic = ic or initial_fields(p["nx"], p["ny"], seed=kw.pop("seed", 0))
+    s.init_fields(ic["phi"], ic["qxx"], ic["qxy"], kw.get("u_a"), kw.get("u_p"))
+    return s
+
+
+def test_error_codes(gpu):
+    say("case: error codes")
+    import paper_2511_00445_amd as T
+    p = workload_params("small_64")
+    with pytest.raises(T.TfanError) as e:
+        T.Sim(dict(p, tau_p=0.4))
+    assert e.value.code == T.TFAN_EINVAL
+    s = T.Sim(p)
+    bad = np.zeros((64, 64))
+    bad[3, 4] = np.nan
+    with pytest.raises(T.TfanError) as e:
+        s.init_fields(bad, bad * 0, bad * 0)
+    assert e.value.code == T.TFAN_EINVAL
+    with pytest.raises(T.TfanError) as e:
+        s.step(-1)
+    assert e.value.code == T.TFAN_EINVAL
+    with pytest.raises(T.TfanError) as e:
+        s.set_state(np.zeros(17, np.uint8))
+    assert e.value.code == T.TFAN_EINVAL
+    buf = np.zeros(10, np.uint8)
+    rc = s.lib.tfan_get_state(s.handle, buf.ctypes.data_as(ctypes.c_void_p), buf.size)
+    assert rc == T.TFAN_ENOMEM
+
+
+def test_health_flags(gpu):
+    say("case: nonfinite and unstable flags")
+    import paper_2511_00445_amd as T
+    p = workload_params("small_64")
+    s = make(p)
+    st = s.get_state()
+    f = st[8:].view(np.float32).copy()
+    f[12345] = np.nan                       # one population, forced from the host
+    st2 = np.concatenate([st[:8], f.view(np.uint8)])
+    s.set_state(st2)
+    d = s.diagnostics()
+    assert d["status"] == T.TFAN_ENONFINITE and d["nonfinite"] >= 1
+    z = np.zeros((64, 64))
+    fast = np.array([np.full((64, 64), 0.35), z])
+    s2 = make(p, u_a=fast)
+    d2 = s2.diagnostics()
+    assert d2["status"] == T.TFAN_EUNSTABLE and d2["umax"] > 0.3
+
+
+def test_determinism_and_checkpoint(gpu):
+    say("case: determinism and checkpoint")
+    p = base_params(72, 40, zeta=0.02, lam=1.2)
+    ic = initial_fields(72, 40, seed=3, phi_noise=0.3, S0=0.2)
+    a, b = make(p, ic), make(p, ic)
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.get_state(), b.get_state())
+    ck = a.get_state()
+    a.step(0)
+    assert np.array_equal(a.get_state(), ck)        # zero steps: nothing changes
+    a.step(15)
+    ref = a.get_state()
+    b.set_state(ck)
+    assert b.step_count() == 30
+    b.step(15)
+    assert np.array_equal(b.get_state(), ref)
+    assert b.step_count() == 45
+
+
+def test_gpu_shear_wave_viscosity(gpu):
+    say("case: shear wave on the GPU")
+    N = 64
+    p = base_params(8, N, zeta=0.0, gamma=0.0, lam=0.0)
+    y = np.arange(N)[:, None] * np.ones((1, 8))
+    mode = np.sin(2 * np.pi * y / N)
+    u0 = np.array([1e-3 * mode, 0 * y])
+    z = np.zeros((N, 8))
+    s = make(p, dict(phi=z, qxx=z, qxy=z), u_a=u0, u_p=u0)
+    amps = []
+    for t in (20, 100):
+        s.step(t - s.step_count())
+        amps.append((s.get_fields()["u_a"][0] * mode).sum() / (mode ** 2).sum())
+    rate = np.log(amps[0] / amps[1]) / 80.0
+    nu = 0.5 / 3.0
+    assert abs(rate / (nu * (2 * np.pi / N) ** 2) - 1) < 1e-4
+
+
+def test_gpu_drag_trapezoid(gpu):
+    say("case: drag trapezoid on the GPU")
+    n, phibar, gamma = 16, 0.4, 0.5
+    p = base_params(n, n, zeta=0.0, gamma=gamma)
+    z = np.zeros((n, n))
+    ua = np.array([np.full((n, n), 3e-3), np.full((n, n), -1e-3)])
+    s = make(p, dict(phi=z + phibar, qxx=z, qxy=z), u_a=ua)
+    beta = gamma * 0.25 * (1 + phibar) * (1 - phibar)
+    r = (1 - beta) / (1 + beta)
+    du0 = np.array([3e-3, -1e-3]) / (1 + beta)  # u_a - u_p at step 0 (Guo velocity)
+    s.step(10)
+    f = s.get_fields()
+    du = (f["u_a"] - f["u_p"])[:, 0, 0]
+    np.testing.assert_allclose(du, du0 * r ** 10, rtol=2e-6)
+
+
+def test_gpu_phi_mass_drift(gpu):
+    say("case: phi mass drift, 1000 steps")
+    p = workload_params("small_64", zeta=0.02)
+    ic = initial_fields(64, 64, seed=5, phi_mean=0.3, phi_noise=0.3)
+    s = make(p, ic)
+    d0 = s.diagnostics()
+    s.step(1000)
+    d1 = s.diagnostics()
+    drift = abs(d1["phi_sum"] - d0["phi_sum"]) / np.abs(ic["phi"]).sum()
+    say(f"phi mass relative drift after 1000 float32 steps: {drift:.3e}")
+    assert drift < 1e-5
+    assert abs(d1["mass_a"] - d0["mass_a"]) < 1e-6 * d0["mass_a"]
+
+
+def test_kernel_timing_api(gpu):
+    say("case: kernel timing")
+    s = make(workload_params("small_64"))
+    s.kernel_timing(1000)
+    s.step(10)
+    t = s.kernel_times()
+    assert t["collide"][1] == 10 and t["collide"][0] > 0
+    assert sum(c for _, c in t.values()) >= 20
+    s.kernel_timing(0)

@@ -58,7 +58,7 @@ typedef enum tfan_status {
 enum { TFAN_STORAGE_F32 = 0 };
 
 /* Problem statement (Model and Numerical Simulation sections).  Limits:
- * 8 <= nx, ny <= 32768, nx*ny <= 2^28, tau > 1/2, 1 <= n_sub <= 64, all reals
+ * 8 <= nx, ny <= 32768, nx*ny <= 2^28, tau > 1/2, 1 <= n_sub <= 8, all reals
  * finite, rho0 > 0, M >= 0, K >= 0, Gamma >= 0, gamma >= 0, kappa >= 0. */
 typedef struct tfan_params {
   int32_t nx, ny;      /* periodic grid                                          */

@@ -54,6 +54,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2511_00445_amd.build`")
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes libtfan.so bind to that one copy instead of a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     sigs = {
         "tfan_check_params": (ctypes.c_int, [_P(tfan_params)]),

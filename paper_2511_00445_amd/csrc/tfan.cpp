@@ -59,7 +59,7 @@ std::string check(const tfan_params* p) {
   if (!p) return "params is NULL";
   if (p->nx < 8 || p->ny < 8 || p->nx > 32768 || p->ny > 32768) return "nx, ny must be in [8, 32768]";
   if ((int64_t)p->nx * p->ny > (int64_t(1) << 28)) return "nx * ny must not exceed 2^28";
-  if (p->n_sub < 1 || p->n_sub > 64) return "n_sub must be in [1, 64]";
+  if (p->n_sub < 1 || p->n_sub > 8) return "n_sub must be in [1, 8]";
   if (p->storage != TFAN_STORAGE_F32) return "unsupported storage format";
   const double r[] = {p->rho0, p->tau_a, p->tau_p, p->gamma, p->A_ch, p->kappa, p->M,
                       p->A_ldg, p->C_ldg, p->K, p->lam, p->Gamma, p->zeta};
@@ -270,7 +270,7 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
       hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "collide kernel launch");
     }
-    // sub-steps alternate the phi/Q buffers; the collide above already read state a
+    // sub-steps alternate the phi/Q buffers; the collision above already read state a
     int src = a;
     for (int m = 0; m < s->dp.n_sub; ++m) {
       TimedLaunch t(s, tfan::K_FD);
@@ -278,7 +278,7 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
       if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
       src = 1 - src;
     }
-    // the new state: populations in b, fields in src; keep them under one index
+    // keep the new populations and fields under one index
     if (src != b) {
       hipError_t e = hipMemcpyAsync(s->phi[b], s->phi[src], (size_t)s->dp.n * sizeof(float),
                                     hipMemcpyDeviceToDevice, s->stream);

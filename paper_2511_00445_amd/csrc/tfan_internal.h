@@ -47,6 +47,7 @@ hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevSta
                        hipStream_t st);
 hipError_t launch_collide(const DevParams& P, DevState in, float* f_out, float* u_out /*[4][n]*/,
                           hipStream_t st);
+// One finite-difference sub-step.
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
                      hipStream_t st);
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: drho_a, drho_p, u_a, u_p*/,

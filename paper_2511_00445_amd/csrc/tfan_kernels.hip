@@ -65,98 +65,6 @@ __device__ __forceinline__ Stress nematic_stress(float qxx, float qxy, float qxx
   return st;
 }
 
-// Everything one site needs before collision: pulled populations, densities,
-// half-force velocities and total forces of both fluids.
-struct Site {
-  float fa[9], fp[9];
-  float dra, drp;        // rho - rho0
-  float uax, uay, upx, upy;
-  float Fax, Fay, Fpx, Fpy;
-  float c1, c2;
-};
-
-__device__ __forceinline__ void site_macroscopic(const DevParams& P, const DevState& in, int x,
-                                                 int y, Site& S) {
-  const int nx = P.nx, ny = P.ny, n = P.n;
-  const int xm1 = wrapi(x - 1, nx), xp1 = wrapi(x + 1, nx);
-  const int xm2 = wrapi(x - 2, nx), xp2 = wrapi(x + 2, nx);
-  const int r0 = y * nx, rm1 = wrapi(y - 1, ny) * nx, rp1 = wrapi(y + 1, ny) * nx;
-  const int rm2 = wrapi(y - 2, ny) * nx, rp2 = wrapi(y + 2, ny) * nx;
-  const float* __restrict__ ph = in.phi;
-  const float* __restrict__ qx = in.q;
-  const float* __restrict__ qy = in.q + n;
-#define TFAN_LD3(name, off)                                                  \
-  const float p##name = ph[off], x##name = qx[off], y##name = qy[off];
-  TFAN_LD3(C, r0 + x)
-  TFAN_LD3(E, r0 + xp1)
-  TFAN_LD3(W, r0 + xm1)
-  TFAN_LD3(N, rp1 + x)
-  TFAN_LD3(S, rm1 + x)
-  TFAN_LD3(EE, r0 + xp2)
-  TFAN_LD3(WW, r0 + xm2)
-  TFAN_LD3(NN, rp2 + x)
-  TFAN_LD3(SS, rm2 + x)
-  TFAN_LD3(NE, rp1 + xp1)
-  TFAN_LD3(NW, rp1 + xm1)
-  TFAN_LD3(SE, rm1 + xp1)
-  TFAN_LD3(SW, rm1 + xm1)
-#undef TFAN_LD3
-  // chemical potential and stress at the four neighbours
-  const float muE = chem_pot(pE, pEE, pC, pNE, pSE, P);
-  const float muW = chem_pot(pW, pC, pWW, pNW, pSW, P);
-  const float muN = chem_pot(pN, pNE, pNW, pNN, pC, P);
-  const float muS = chem_pot(pS, pSE, pSW, pC, pSS, P);
-  const Stress sE = nematic_stress(xE, yE, xEE, yEE, xC, yC, xNE, yNE, xSE, ySE, 0.5f * (1.f + pE), P);
-  const Stress sW = nematic_stress(xW, yW, xC, yC, xWW, yWW, xNW, yNW, xSW, ySW, 0.5f * (1.f + pW), P);
-  const Stress sN = nematic_stress(xN, yN, xNE, yNE, xNW, yNW, xNN, yNN, xC, yC, 0.5f * (1.f + pN), P);
-  const Stress sS = nematic_stress(xS, yS, xSE, ySE, xSW, ySW, xC, yC, xSS, ySS, 0.5f * (1.f + pS), P);
-  // F_i = d_j sigma_ij
-  const float Fx = 0.5f * (sE.xx - sW.xx) + 0.5f * ((sN.s + sN.a) - (sS.s + sS.a));
-  const float Fy = 0.5f * ((sE.s - sE.a) - (sW.s - sW.a)) + 0.5f * (sN.yy - sS.yy);
-  const float c1 = 0.5f * (1.f + pC), c2 = 0.5f * (1.f - pC);
-  // capillary force -phi grad(mu), shared c1 : c2
-  const float fchx = -pC * 0.5f * (muE - muW);
-  const float fchy = -pC * 0.5f * (muN - muS);
-  const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
-  const float Gpx = c2 * fchx, Gpy = c2 * fchy;
-
-  // pull both population sets and take moments
-  float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int sx = (CX[i] == 0) ? x : (CX[i] > 0 ? xm1 : xp1);
-    const int sy = (CY[i] == 0) ? r0 : (CY[i] > 0 ? rm1 : rp1);
-    const float a = in.f[(size_t)i * n + sy + sx];
-    const float p = in.f[(size_t)(9 + i) * n + sy + sx];
-    S.fa[i] = a;
-    S.fp[i] = p;
-    dra += a;
-    drp += p;
-    if (CX[i] != 0) { mxa += CX[i] * a; mxp += CX[i] * p; }
-    if (CY[i] != 0) { mya += CY[i] * a; myp += CY[i] * p; }
-  }
-  const float rho_a = P.rho0 + dra, rho_p = P.rho0 + drp;
-  // Guo half-force velocities with the drag implicit: per component
-  // [[rho_a + g, -g], [-g, rho_p + g]] [u_a; u_p] = [m_a + G_a/2; m_p + G_p/2]
-  const float g = 0.5f * P.gamma * c1 * c2;
-  const float inv = 1.f / (rho_a * rho_p + g * (rho_a + rho_p));
-  const float bax = mxa + 0.5f * Gax, bay = mya + 0.5f * Gay;
-  const float bpx = mxp + 0.5f * Gpx, bpy = myp + 0.5f * Gpy;
-  S.uax = ((rho_p + g) * bax + g * bpx) * inv;
-  S.uay = ((rho_p + g) * bay + g * bpy) * inv;
-  S.upx = (g * bax + (rho_a + g) * bpx) * inv;
-  S.upy = (g * bay + (rho_a + g) * bpy) * inv;
-  const float fdx = 2.f * g * (S.upx - S.uax), fdy = 2.f * g * (S.upy - S.uay);
-  S.Fax = Gax + fdx;
-  S.Fay = Gay + fdy;
-  S.Fpx = Gpx - fdx;
-  S.Fpy = Gpy - fdy;
-  S.dra = dra;
-  S.drp = drp;
-  S.c1 = c1;
-  S.c2 = c2;
-}
-
 // BGK collision with the Guo source for one fluid, written post-collision:
 // f* = f + (f^eq - f)/tau + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F,
 // all populations shifted by -w_i rho0.
@@ -176,93 +84,272 @@ __device__ __forceinline__ void collide_fluid(const float f[9], float dr, float 
   }
 }
 
-__global__ void __launch_bounds__(256) k_collide(DevParams P, DevState in, float* __restrict__ fout,
-                                                 float* __restrict__ uout) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= P.nx || y >= P.ny) return;
-  Site S;
-  site_macroscopic(P, in, x, y, S);
-  const int idx = y * P.nx + x, n = P.n;
-  collide_fluid(S.fa, S.dra, S.uax, S.uay, S.Fax, S.Fay, P.om_a, P.gk_a, P.rho0, fout, n, idx);
-  collide_fluid(S.fp, S.drp, S.upx, S.upy, S.Fpx, S.Fpy, P.om_p, P.gk_p, P.rho0, fout + (size_t)9 * n,
-                n, idx);
-  uout[idx] = S.uax;
-  uout[n + idx] = S.uay;
-  uout[2 * n + idx] = S.c1 * S.uax + S.c2 * S.upx;
-  uout[3 * n + idx] = S.c1 * S.uay + S.c2 * S.upy;
+// ---------------------------------------------------------------------------
+// Collision kernel.  A block owns a 64 x 8 tile of sites (256 threads, two rows
+// each).  phi and Q are staged with a halo of 2; mu and the nematic stress are
+// evaluated once per site on the tile plus a halo of 1 and shared through LDS;
+// the 18 population pulls are issued before the staging so their latency hides
+// behind it.  FIELDS = true evaluates the same velocities and densities and
+// writes them out instead of colliding (get_fields / diagnostics).
+// ---------------------------------------------------------------------------
+constexpr int CT_X = 64, CT_Y = 8, CT_THREADS = 256;
+constexpr int CT_ROWS_PER_PASS = CT_THREADS / CT_X;  // 4
+constexpr int CT_SITES = CT_Y / CT_ROWS_PER_PASS;    // 2 sites per thread
+constexpr int PX = CT_X + 4, PY = CT_Y + 4;          // phi/Q staging, halo 2
+constexpr int SX = CT_X + 2, SY = CT_Y + 2;          // mu/stress region, halo 1
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Launching 8 * ceil(tiles / 8) workgroups and giving XCD k the contiguous tile
+// range [k * per, (k + 1) * per) keeps spatial neighbours (which share the
+// cache lines of their halos and of the shifted population pulls) in one L2.
+// Returns the row-major tile index of this workgroup, or -1 for a spare one.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int tiles) {
+  const int per = (tiles + kXcds - 1) / kXcds;
+  const int t = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  return t < tiles ? t : -1;
+}
+inline unsigned xcd_grid(int tiles) { return (unsigned)(kXcds * ((tiles + kXcds - 1) / kXcds)); }
+
+// Periodic index for any offset (tiles of small grids wrap more than once).
+__device__ __forceinline__ int wrap_any(int i, int n) {
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
 }
 
-__global__ void __launch_bounds__(256) k_fields(DevParams P, DevState in, float* __restrict__ aux) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= P.nx || y >= P.ny) return;
-  Site S;
-  site_macroscopic(P, in, x, y, S);
-  const int idx = y * P.nx + x, n = P.n;
-  aux[idx] = S.dra;  // density deviations: rho0 is added in float64 by the reader
-  aux[n + idx] = S.drp;
-  aux[2 * n + idx] = S.uax;
-  aux[3 * n + idx] = S.uay;
-  aux[4 * n + idx] = S.upx;
-  aux[5 * n + idx] = S.upy;
+
+// Raw buffer access to one float32 plane of n elements: a scalar resource plus
+// a 32-bit byte offset per lane, so planes indexed alike share one offset
+// register and small constant offsets fold into the instruction.
+using Plane = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ Plane plane(const float* p, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, n * 4, 0x00020000);
+}
+__device__ __forceinline__ float ldg(Plane r, unsigned idx) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, idx * 4u, 0, 0));
+}
+__device__ __forceinline__ void stg(Plane r, unsigned idx, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, idx * 4u, 0, 0);
 }
 
-// One forward-Euler sub-step of the Cahn-Hilliard (Model, Eq. 1) and
-// Beris-Edwards (Model, Eqs. 11-12) equations with frozen u_a, u_c.
-__global__ void __launch_bounds__(256) k_fd(DevParams P, DevState in, DevState out,
-                                            const float* __restrict__ U) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  if (x >= P.nx || y >= P.ny) return;
-  const int nx = P.nx, ny = P.ny, n = P.n;
-  const int xm1 = wrapi(x - 1, nx), xp1 = wrapi(x + 1, nx);
-  const int xm2 = wrapi(x - 2, nx), xp2 = wrapi(x + 2, nx);
-  const int r0 = y * nx, rm1 = wrapi(y - 1, ny) * nx, rp1 = wrapi(y + 1, ny) * nx;
-  const int rm2 = wrapi(y - 2, ny) * nx, rp2 = wrapi(y + 2, ny) * nx;
-  const float* __restrict__ ph = in.phi;
-  // --- Cahn-Hilliard: phi += h [ -div(phi u_c) + M lap(mu) ]
-  const float pC = ph[r0 + x], pE = ph[r0 + xp1], pW = ph[r0 + xm1], pN = ph[rp1 + x], pS = ph[rm1 + x];
-  const float pEE = ph[r0 + xp2], pWW = ph[r0 + xm2], pNN = ph[rp2 + x], pSS = ph[rm2 + x];
-  const float pNE = ph[rp1 + xp1], pNW = ph[rp1 + xm1], pSE = ph[rm1 + xp1], pSW = ph[rm1 + xm1];
-  const float muC = chem_pot(pC, pE, pW, pN, pS, P);
-  const float muE = chem_pot(pE, pEE, pC, pNE, pSE, P);
-  const float muW = chem_pot(pW, pC, pWW, pNW, pSW, P);
-  const float muN = chem_pot(pN, pNE, pNW, pNN, pC, P);
-  const float muS = chem_pot(pS, pSE, pSW, pC, pSS, P);
-  const float* __restrict__ ucx = U + 2 * n;
-  const float* __restrict__ ucy = U + 3 * n;
-  const float div = 0.5f * (pE * ucx[r0 + xp1] - pW * ucx[r0 + xm1]) +
-                    0.5f * (pN * ucy[rp1 + x] - pS * ucy[rm1 + x]);
-  const float lapmu = (muE + muW) + (muN + muS) - 4.f * muC;
-  out.phi[r0 + x] = pC + P.h * (P.M * lapmu - div);
-
-  // --- Beris-Edwards: Q += h Proj[ -u_a.grad Q + S(W, Q) + Gamma H ]
-  const float* __restrict__ qx = in.q;
-  const float* __restrict__ qy = in.q + n;
-  const float xC = qx[r0 + x], xE = qx[r0 + xp1], xW = qx[r0 + xm1], xN = qx[rp1 + x], xS = qx[rm1 + x];
-  const float yC = qy[r0 + x], yE = qy[r0 + xp1], yW = qy[r0 + xm1], yN = qy[rp1 + x], yS = qy[rm1 + x];
-  const float* __restrict__ uax = U;
-  const float* __restrict__ uay = U + n;
-  const float ux = uax[r0 + x], uy = uay[r0 + x];
-  // W_ij = d_j u_a,i
-  const float wxx = 0.5f * (uax[r0 + xp1] - uax[r0 + xm1]);
-  const float wxy = 0.5f * (uax[rp1 + x] - uax[rm1 + x]);
-  const float wyx = 0.5f * (uay[r0 + xp1] - uay[r0 + xm1]);
-  const float wyy = 0.5f * (uay[rp1 + x] - uay[rm1 + x]);
+// One forward-Euler Beris-Edwards update of (Qxx, Qxy) (Model, Eqs. 11-12) at a
+// site: Q += h Proj[ -u_a.grad Q + S(W, Q) + Gamma H ], with W_ij = d_j u_a,i given.
+// The symmetric traceless part of S(W, Q) in two dimensions is
+// lam E_dev + lam tr(W) Q - 2 lam (Q:E) Q + (Om.Q - Q.Om).
+__device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, float2 qn, float2 qs,
+                                            float2 u, float wxx, float wxy, float wyx, float wyy,
+                                            float h, const DevParams& P) {
   const float d = 0.5f * (wxx - wyy), e = 0.5f * (wxy + wyx), tr = wxx + wyy;
   const float om = 0.5f * (wxy - wyx);
-  const float b = P.A_ldg + P.halfC * (2.f * (xC * xC + yC * yC));
-  const float hxx = P.K * ((xE + xW) + (xN + xS) - 4.f * xC) - b * xC;
-  const float hxy = P.K * ((yE + yW) + (yN + yS) - 4.f * yC) - b * yC;
-  // symmetric traceless part of S(W, Q): lam E_dev + lam tr(W) Q - 2 lam (Q:E) Q + (Om.Q - Q.Om)
-  const float g = P.lam * (tr - 4.f * (xC * d + yC * e));
-  const float sxx = P.lam * d + g * xC + 2.f * om * yC;
-  const float sxy = P.lam * e + g * yC - 2.f * om * xC;
-  const float advx = -(ux * 0.5f * (xE - xW) + uy * 0.5f * (xN - xS));
-  const float advy = -(ux * 0.5f * (yE - yW) + uy * 0.5f * (yN - yS));
-  out.q[r0 + x] = xC + P.h * (advx + sxx + P.Gamma * hxx);
-  out.q[n + r0 + x] = yC + P.h * (advy + sxy + P.Gamma * hxy);
+  const float b = P.A_ldg + P.halfC * (2.f * (q.x * q.x + q.y * q.y));
+  const float hxx = P.K * ((qe.x + qw.x) + (qn.x + qs.x) - 4.f * q.x) - b * q.x;
+  const float hxy = P.K * ((qe.y + qw.y) + (qn.y + qs.y) - 4.f * q.y) - b * q.y;
+  const float g = P.lam * (tr - 4.f * (q.x * d + q.y * e));
+  const float sxx = P.lam * d + g * q.x + 2.f * om * q.y;
+  const float sxy = P.lam * e + g * q.y - 2.f * om * q.x;
+  const float advx = -(u.x * 0.5f * (qe.x - qw.x) + u.y * 0.5f * (qn.x - qs.x));
+  const float advy = -(u.x * 0.5f * (qe.y - qw.y) + u.y * 0.5f * (qn.y - qs.y));
+  return make_float2(q.x + h * (advx + sxx + P.Gamma * hxx), q.y + h * (advy + sxy + P.Gamma * hxy));
+}
+
+template <bool FIELDS>
+__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, float* __restrict__ fout,
+                                                        float* __restrict__ uout) {
+  __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
+  __shared__ float smu[SY][SX], sxx[SY][SX], syy[SY][SX], ssy[SY][SX], san[SY][SX];
+  const int nx = P.nx, ny = P.ny, n = P.n;
+  const int gx = (nx + CT_X - 1) / CT_X;
+  const int tile = xcd_tile(gx * ((ny + CT_Y - 1) / CT_Y));
+  if (tile < 0) return;  // whole workgroup, before any barrier
+  const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
+  const int x0 = (tile % gx) * CT_X, y0 = (tile / gx) * CT_Y;
+
+  // 1. pull both population sets of this thread's sites: f_i(x) = f*_i(x - c_i)
+  float fa[CT_SITES][9], fp[CT_SITES][9];
+  const int x = x0 + tx;
+  const bool xin = x < nx;
+  const int xc = xin ? x : 0;
+  const int xm1 = wrapi(xc - 1, nx), xp1 = wrapi(xc + 1, nx);
+#pragma unroll
+  for (int s = 0; s < CT_SITES; ++s) {
+    const int y = y0 + ty + CT_ROWS_PER_PASS * s;
+    const int yc = (y < ny) ? y : 0;
+    const int r0 = yc * nx, rm1 = wrapi(yc - 1, ny) * nx, rp1 = wrapi(yc + 1, ny) * nx;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int sx = (CX[i] == 0) ? xc : (CX[i] > 0 ? xm1 : xp1);
+      const int sy = (CY[i] == 0) ? r0 : (CY[i] > 0 ? rm1 : rp1);
+      fa[s][i] = in.f[(size_t)i * n + sy + sx];
+      fp[s][i] = in.f[(size_t)(9 + i) * n + sy + sx];
+    }
+  }
+  // 2. stage phi, Qxx, Qxy on the tile with a halo of 2
+  for (int c = threadIdx.x; c < PX * PY; c += CT_THREADS) {
+    const int cy = c / PX, cx = c - cy * PX;
+    const int g = wrap_any(y0 - 2 + cy, ny) * nx + wrap_any(x0 - 2 + cx, nx);
+    sph[cy][cx] = in.phi[g];
+    sqx[cy][cx] = in.q[g];
+    sqy[cy][cx] = in.q[n + g];
+  }
+  __syncthreads();
+  // 3. chemical potential and nematic stress on the tile plus a halo of 1
+  for (int c = threadIdx.x; c < SX * SY; c += CT_THREADS) {
+    const int sy = c / SX, sx = c - sy * SX;
+    const int py = sy + 1, px = sx + 1;
+    const float p = sph[py][px];
+    smu[sy][sx] = chem_pot(p, sph[py][px + 1], sph[py][px - 1], sph[py + 1][px], sph[py - 1][px], P);
+    const Stress st = nematic_stress(sqx[py][px], sqy[py][px], sqx[py][px + 1], sqy[py][px + 1],
+                                     sqx[py][px - 1], sqy[py][px - 1], sqx[py + 1][px], sqy[py + 1][px],
+                                     sqx[py - 1][px], sqy[py - 1][px], 0.5f * (1.f + p), P);
+    sxx[sy][sx] = st.xx;
+    syy[sy][sx] = st.yy;
+    ssy[sy][sx] = st.s;
+    san[sy][sx] = st.a;
+  }
+  __syncthreads();
+  // 4. forces, Guo velocities with implicit drag, collision (or field output)
+#pragma unroll
+  for (int s = 0; s < CT_SITES; ++s) {
+    const int ly = ty + CT_ROWS_PER_PASS * s;
+    const int y = y0 + ly;
+    if (!xin || y >= ny) continue;
+    const int sy = ly + 1, sx = tx + 1;
+    // F_i = d_j sigma_ij with sigma_xy = s + a, sigma_yx = s - a
+    const float Fx = 0.5f * (sxx[sy][sx + 1] - sxx[sy][sx - 1]) +
+                     0.5f * ((ssy[sy + 1][sx] + san[sy + 1][sx]) - (ssy[sy - 1][sx] + san[sy - 1][sx]));
+    const float Fy = 0.5f * ((ssy[sy][sx + 1] - san[sy][sx + 1]) - (ssy[sy][sx - 1] - san[sy][sx - 1])) +
+                     0.5f * (syy[sy + 1][sx] - syy[sy - 1][sx]);
+    const float pC = sph[ly + 2][tx + 2];
+    const float c1 = 0.5f * (1.f + pC), c2 = 0.5f * (1.f - pC);
+    // capillary force -phi grad(mu), shared c1 : c2
+    const float fchx = -pC * 0.5f * (smu[sy][sx + 1] - smu[sy][sx - 1]);
+    const float fchy = -pC * 0.5f * (smu[sy + 1][sx] - smu[sy - 1][sx]);
+    const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
+    const float Gpx = c2 * fchx, Gpy = c2 * fchy;
+    float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      dra += fa[s][i];
+      drp += fp[s][i];
+      if (CX[i] != 0) { mxa += CX[i] * fa[s][i]; mxp += CX[i] * fp[s][i]; }
+      if (CY[i] != 0) { mya += CY[i] * fa[s][i]; myp += CY[i] * fp[s][i]; }
+    }
+    const float rho_a = P.rho0 + dra, rho_p = P.rho0 + drp;
+    // per component [[rho_a + g, -g], [-g, rho_p + g]] [u_a; u_p] = [m_a + G_a/2; m_p + G_p/2]
+    const float g = 0.5f * P.gamma * c1 * c2;
+    const float inv = 1.f / (rho_a * rho_p + g * (rho_a + rho_p));
+    const float bax = mxa + 0.5f * Gax, bay = mya + 0.5f * Gay;
+    const float bpx = mxp + 0.5f * Gpx, bpy = myp + 0.5f * Gpy;
+    const float uax = ((rho_p + g) * bax + g * bpx) * inv;
+    const float uay = ((rho_p + g) * bay + g * bpy) * inv;
+    const float upx = (g * bax + (rho_a + g) * bpx) * inv;
+    const float upy = (g * bay + (rho_a + g) * bpy) * inv;
+    const int idx = y * nx + x;
+    if (FIELDS) {
+      uout[idx] = dra;  // density deviations: rho0 is added in float64 by the reader
+      uout[n + idx] = drp;
+      uout[2 * n + idx] = uax;
+      uout[3 * n + idx] = uay;
+      uout[4 * n + idx] = upx;
+      uout[5 * n + idx] = upy;
+    } else {
+      const float fdx = 2.f * g * (upx - uax), fdy = 2.f * g * (upy - uay);
+      collide_fluid(fa[s], dra, uax, uay, Gax + fdx, Gay + fdy, P.om_a, P.gk_a, P.rho0, fout, n, idx);
+      collide_fluid(fp[s], drp, upx, upy, Gpx - fdx, Gpy - fdy, P.om_p, P.gk_p, P.rho0,
+                    fout + (size_t)9 * n, n, idx);
+      uout[idx] = uax;
+      uout[n + idx] = uay;
+      uout[2 * n + idx] = c1 * uax + c2 * upx;
+      uout[3 * n + idx] = c1 * uay + c2 * upy;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One forward-Euler sub-step of the Cahn-Hilliard (Model, Eq. 1) and
+// Beris-Edwards (Model, Eqs. 11-12) equations with u_a and u_c frozen.  Each
+// thread updates R consecutive rows of one column, so the stencils of
+// neighbouring rows share their loads and their chemical-potential values.
+// ---------------------------------------------------------------------------
+#ifndef TFAN_FD_R
+#define TFAN_FD_R 4
+#endif
+constexpr int FD_TX = 64, FD_TY = 4, FD_R = TFAN_FD_R;
+
+template <int R>
+__global__ void __launch_bounds__(FD_TX * FD_TY) k_fd(DevParams P, DevState in, DevState out,
+                                                       const float* __restrict__ U) {
+  const int nx = P.nx, ny = P.ny, n = P.n;
+  const int gx = (nx + FD_TX - 1) / FD_TX;
+  const int tile = xcd_tile(gx * ((ny + FD_TY * R - 1) / (FD_TY * R)));
+  if (tile < 0) return;
+  const int x = (tile % gx) * FD_TX + threadIdx.x;
+  const int y0 = ((tile / gx) * FD_TY + threadIdx.y) * R;
+  if (x >= nx || y0 >= ny) return;
+  const unsigned xc = x, xm1 = wrapi(x - 1, nx), xp1 = wrapi(x + 1, nx);
+  const unsigned xm2 = wrapi(x - 2, nx), xp2 = wrapi(x + 2, nx);
+  unsigned row[R + 4];  // rows y0 - 2 .. y0 + R + 1 (offsets below n: n >= 8 > R + 1)
+#pragma unroll
+  for (int j = 0; j < R + 4; ++j) row[j] = (unsigned)wrapi(y0 - 2 + j, ny) * (unsigned)nx;
+  const Plane ph = plane(in.phi, n), ophi = plane(out.phi, n);
+  // ---- Cahn-Hilliard: phi += h [ -div(phi u_c) + M lap(mu) ]
+  float pc[R + 4], pe[R + 2], pw[R + 2], pee[R], pww[R];
+#pragma unroll
+  for (int j = 0; j < R + 4; ++j) pc[j] = ldg(ph, row[j] + xc);        // rows y0-2+j
+#pragma unroll
+  for (int j = 0; j < R + 2; ++j) {                                     // rows y0-1+j
+    pe[j] = ldg(ph, row[j + 1] + xp1);
+    pw[j] = ldg(ph, row[j + 1] + xm1);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {                                         // rows y0+j
+    pee[j] = ldg(ph, row[j + 2] + xp2);
+    pww[j] = ldg(ph, row[j + 2] + xm2);
+  }
+  float mc[R + 2], me[R], mw[R];
+#pragma unroll
+  for (int j = 0; j < R + 2; ++j) mc[j] = chem_pot(pc[j + 1], pe[j], pw[j], pc[j + 2], pc[j], P);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    me[j] = chem_pot(pe[j + 1], pee[j], pc[j + 2], pe[j + 2], pe[j], P);
+    mw[j] = chem_pot(pw[j + 1], pc[j + 2], pww[j], pw[j + 2], pw[j], P);
+  }
+  const Plane ucx = plane(U + 2 * n, n), ucy = plane(U + 3 * n, n);
+  float cy[R + 2];
+#pragma unroll
+  for (int j = 0; j < R + 2; ++j) cy[j] = ldg(ucy, row[j + 1] + xc);  // rows y0-1+j
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (y0 + j >= ny) break;
+    const float cxe = ldg(ucx, row[j + 2] + xp1), cxw = ldg(ucx, row[j + 2] + xm1);
+    const float div = 0.5f * (pe[j + 1] * cxe - pw[j + 1] * cxw) + 0.5f * (pc[j + 3] * cy[j + 2] - pc[j + 1] * cy[j]);
+    const float lapmu = (me[j] + mw[j]) + (mc[j + 2] + mc[j]) - 4.f * mc[j + 1];
+    stg(ophi, row[j + 2] + xc, pc[j + 2] + P.h * (P.M * lapmu - div));
+  }
+  // ---- Beris-Edwards: Q += h Proj[ -u_a.grad Q + S(W, Q) + Gamma H ]
+  const Plane qx = plane(in.q, n), qy = plane(in.q + n, n), oqx = plane(out.q, n), oqy = plane(out.q + n, n);
+  const Plane ax = plane(U, n), ay = plane(U + n, n);
+  float2 qc[R + 2], ac[R + 2];                                          // rows y0-1+j
+#pragma unroll
+  for (int j = 0; j < R + 2; ++j) {
+    const unsigned o = row[j + 1] + xc;
+    qc[j] = make_float2(ldg(qx, o), ldg(qy, o));
+    ac[j] = make_float2(ldg(ax, o), ldg(ay, o));
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    if (y0 + j >= ny) break;
+    const unsigned oe = row[j + 2] + xp1, ow = row[j + 2] + xm1;
+    const float2 qe = make_float2(ldg(qx, oe), ldg(qy, oe)), qw = make_float2(ldg(qx, ow), ldg(qy, ow));
+    const float2 ue = make_float2(ldg(ax, oe), ldg(ay, oe)), uw = make_float2(ldg(ax, ow), ldg(ay, ow));
+    const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (ac[j + 2].x - ac[j].x);
+    const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (ac[j + 2].y - ac[j].y);
+    const float2 nq = be_update(qc[j + 1], qe, qw, qc[j + 2], qc[j], ac[j + 1], wxx, wxy, wyx, wyy, P.h, P);
+    const unsigned o = row[j + 2] + xc;
+    stg(oqx, o, nq.x);
+    stg(oqy, o, nq.y);
+  }
 }
 
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
@@ -415,21 +502,25 @@ hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hip
   return hipGetLastError();
 }
 
+inline int collide_tiles(const DevParams& P) {
+  return ((P.nx + CT_X - 1) / CT_X) * ((P.ny + CT_Y - 1) / CT_Y);
+}
+
 hipError_t launch_collide(const DevParams& P, DevState in, float* f_out, float* u_out, hipStream_t st) {
-  const dim3 blk(64, 4);
-  hipLaunchKernelGGL(k_collide, grid2d(P, blk), blk, 0, st, P, in, f_out, u_out);
+  hipLaunchKernelGGL(k_collide<false>, dim3(xcd_grid(collide_tiles(P))), dim3(CT_THREADS), 0, st, P, in,
+                     f_out, u_out);
   return hipGetLastError();
 }
 
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, hipStream_t st) {
-  const dim3 blk(64, 4);
-  hipLaunchKernelGGL(k_fd, grid2d(P, blk), blk, 0, st, P, in, out, u);
+  const int tiles = ((P.nx + FD_TX - 1) / FD_TX) * ((P.ny + FD_TY * FD_R - 1) / (FD_TY * FD_R));
+  hipLaunchKernelGGL(k_fd<FD_R>, dim3(xcd_grid(tiles)), dim3(FD_TX, FD_TY), 0, st, P, in, out, u);
   return hipGetLastError();
 }
 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
-  const dim3 blk(64, 4);
-  hipLaunchKernelGGL(k_fields, grid2d(P, blk), blk, 0, st, P, in, aux);
+  hipLaunchKernelGGL(k_collide<true>, dim3(xcd_grid(collide_tiles(P))), dim3(CT_THREADS), 0, st, P, in,
+                     nullptr, aux);
   return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ def say(msg):
     sys.stdout.flush()
 
 
-def rel_l2(g, o, floor=1e-10):
+def rel_l2(g, o, floor=1e-8):
     """||g - o|| / ||o||, with ||o|| floored at floor * sqrt(size) so that fields
     that are zero up to rounding (the density deviations at rest) compare by an
     absolute bound instead."""

@@ -1,0 +1,26 @@
+"""P17: the plain-C oracle and the numpy oracle are two independent codings of the
+same algorithm; they must agree to rounding on random states."""
+import numpy as np
+import pytest
+
+from oracle.coracle import COracle
+from oracle.tfan_oracle import Oracle
+from paper_2511_00445_amd.workloads import base_params, initial_fields, random_velocity
+
+
+@pytest.mark.parametrize("nx,ny,steps,over", [(16, 16, 5, {}), (24, 13, 4, dict(zeta=0.05, lam=2.0, gamma=0.4)),
+                                              (64, 64, 3, dict(n_sub=3, tau_a=0.7, tau_p=1.4, A0=0.1,
+                                                               gamma_ldg=5.0))])
+def test_c_oracle_matches_numpy_oracle(nx, ny, steps, over):
+    p = base_params(nx, ny, **over)
+    ic = initial_fields(nx, ny, seed=17, phi_mean=0.1, phi_noise=0.5, S0=0.3)
+    ua, up = random_velocity(nx, ny, 18, 5e-3), random_velocity(nx, ny, 19, 5e-3)
+    a, b = Oracle(p), COracle(p)
+    a.init_fields(**ic, u_a=ua, u_p=up)
+    b.init_fields(**ic, u_a=ua, u_p=up)
+    a.step(steps)
+    b.step(steps)
+    fa, fb = a.get_fields(), b.get_fields()
+    for k in fa:
+        scale = max(np.abs(fa[k]).max(), 1e-30)
+        assert np.abs(fa[k] - fb[k]).max() <= 1e-12 * scale, (k, np.abs(fa[k] - fb[k]).max(), scale)

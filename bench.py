@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="large_2048")
+    ap.add_argument("--storage", choices=("f32", "f16"), default="f32",
+                    help="population storage (f16: binary16 deviations, float32 arithmetic)")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -109,6 +111,7 @@ def main():
     torch.cuda.set_device(0)
     w = WORKLOADS[args.workload]
     p = workload_params(args.workload)
+    p["storage"] = 1 if args.storage == "f16" else 0
     nx, ny = p["nx"], p["ny"]
     ic = initial_fields(nx, ny, seed=w["seeds"][0], phi_mean=w["phi_mean"])
     sim = Sim(p, device="cuda:0")
@@ -141,10 +144,14 @@ def main():
     # dominant kernel: largest total time in the timed region
     name, (ms_tot, count) = max(((k, v) for k, v in ktimes.items() if v[1] > 0), key=lambda kv: kv[1][0])
     avg_s = ms_tot / count / 1e3
-    alg = ALG_BYTES[name] * sites
+    alg_bytes = dict(ALG_BYTES)
+    if p["storage"] == 1:  # populations at 2 bytes
+        alg_bytes["step"] -= 72
+        alg_bytes["collide"] -= 72
+    alg = alg_bytes[name] * sites
     achieved = alg / avg_s / 1e9
-    traffic = measured_traffic(name)
-    step_gbs = ALG_BYTES["step"] * sites * args.steps / wall / 1e9
+    traffic = measured_traffic(name) if p["storage"] == 0 else None
+    step_gbs = alg_bytes["step"] * sites * args.steps / wall / 1e9
     out = {
         "metric": "MLUPS per coupled step",
         "value": round(mlups, 1),
@@ -156,15 +163,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if p["storage"] == 0 else "f16-storage/f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {nx}x{ny} periodic, plain float32 path, "
+        "config": {"workload": f"{args.workload}: {nx}x{ny} periodic, "
+                               f"{'plain float32' if p['storage'] == 0 else 'binary16-storage'} path, "
                                f"zeta={p['zeta']}, n_sub={p['n_sub']}, seed {w['seeds'][0]}",
                    "nx": nx, "ny": ny, "n_sub": p["n_sub"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2)},
-        "step_roofline": {"alg_bytes_per_site": ALG_BYTES["step"], "achieved": round(step_gbs, 1),
+        "step_roofline": {"alg_bytes_per_site": alg_bytes["step"], "achieved": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels_ms": {k: [round(v[0], 3), v[1]] for k, v in ktimes.items() if v[1] > 0},
         "event_region_ms": round(region_ms, 3),

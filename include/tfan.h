@@ -54,8 +54,11 @@ typedef enum tfan_status {
   TFAN_EUNSTABLE = -5   /* diagnostics found max |u| above 0.3 (Mach guard)     */
 } tfan_status;
 
-/* Population storage format. */
-enum { TFAN_STORAGE_F32 = 0 };
+/* Population storage format.  The populations are stored as the deviations
+ * f_i - w_i rho0 from rest; TFAN_STORAGE_F16 keeps them as IEEE binary16
+ * (round to nearest even) and does all arithmetic in float32, halving the
+ * population bytes per step.  phi and Q are float32 in both formats. */
+enum { TFAN_STORAGE_F32 = 0, TFAN_STORAGE_F16 = 1 };
 
 /* Problem statement (Model and Numerical Simulation sections).  Limits:
  * 8 <= nx, ny <= 32768, nx*ny <= 2^28, tau > 1/2, 1 <= n_sub <= 8, all reals
@@ -63,7 +66,7 @@ enum { TFAN_STORAGE_F32 = 0 };
 typedef struct tfan_params {
   int32_t nx, ny;      /* periodic grid                                          */
   int32_t n_sub;       /* finite-difference sub-steps per lattice-Boltzmann step */
-  int32_t storage;     /* TFAN_STORAGE_F32                                       */
+  int32_t storage;     /* TFAN_STORAGE_F32 or TFAN_STORAGE_F16                   */
   double rho0;         /* density of each fluid (rho_1 = rho_2)                  */
   double tau_a, tau_p; /* BGK relaxation times; viscosity (tau - 1/2)/3          */
   double gamma;        /* inter-fluid drag coefficient                           */
@@ -132,7 +135,8 @@ int tfan_get_fields(tfan_sim* s, double* phi, double* qxx, double* qxy,
  * still filled) when the state is broken.  Synchronises the stream. */
 int tfan_diagnostics(tfan_sim* s, tfan_diag* out);
 
-/* Checkpoint: the raw device state (populations, phi, Q, step counter).
+/* Checkpoint: the raw device state (step counter int64, populations in their
+ * storage format, phi, Q as float32).
  * tfan_state_bytes() gives the size; set_state restores it bit for bit. */
 size_t tfan_state_bytes(const tfan_sim* s);
 int tfan_get_state(tfan_sim* s, void* host, size_t bytes);

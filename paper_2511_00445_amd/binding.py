@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtfan.so"
 TFAN_OK, TFAN_EINVAL, TFAN_ENOMEM, TFAN_EHIP, TFAN_ENONFINITE, TFAN_EUNSTABLE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "TFAN_OK", -1: "TFAN_EINVAL", -2: "TFAN_ENOMEM", -3: "TFAN_EHIP",
                 -4: "TFAN_ENONFINITE", -5: "TFAN_EUNSTABLE"}
-TFAN_STORAGE_F32 = 0
+TFAN_STORAGE_F32, TFAN_STORAGE_F16 = 0, 1
 
 
 class tfan_params(ctypes.Structure):

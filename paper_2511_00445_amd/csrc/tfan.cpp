@@ -20,7 +20,8 @@ struct tfan_sim {
   hipStream_t stream = nullptr;
   int device = 0;
   // workspace carve-up
-  float* f[2] = {nullptr, nullptr};    // [18][n] each
+  void* f[2] = {nullptr, nullptr};     // [18][n] each, float32 or binary16
+  size_t pop_bytes = 4;                // bytes per stored population
   float* phi[2] = {nullptr, nullptr};  // [n]
   float* q[2] = {nullptr, nullptr};    // [2][n]
   float* U = nullptr;                  // [4][n]: u_a, u_c of the current step
@@ -60,7 +61,7 @@ std::string check(const tfan_params* p) {
   if (p->nx < 8 || p->ny < 8 || p->nx > 32768 || p->ny > 32768) return "nx, ny must be in [8, 32768]";
   if ((int64_t)p->nx * p->ny > (int64_t(1) << 28)) return "nx * ny must not exceed 2^28";
   if (p->n_sub < 1 || p->n_sub > 8) return "n_sub must be in [1, 8]";
-  if (p->storage != TFAN_STORAGE_F32) return "unsupported storage format";
+  if (p->storage != TFAN_STORAGE_F32 && p->storage != TFAN_STORAGE_F16) return "unsupported storage format";
   const double r[] = {p->rho0, p->tau_a, p->tau_p, p->gamma, p->A_ch, p->kappa, p->M,
                       p->A_ldg, p->C_ldg, p->K, p->lam, p->Gamma, p->zeta};
   for (double v : r)
@@ -84,7 +85,8 @@ Layout layout(const tfan_params* p) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-  for (int k = 0; k < 2; ++k) L.f[k] = take(18 * n * sizeof(float));
+  const size_t pb = p->storage == TFAN_STORAGE_F16 ? 2 : 4;
+  for (int k = 0; k < 2; ++k) L.f[k] = take(18 * n * pb);
   for (int k = 0; k < 2; ++k) L.phi[k] = take(n * sizeof(float));
   for (int k = 0; k < 2; ++k) L.q[k] = take(2 * n * sizeof(float));
   L.U = take(4 * n * sizeof(float));
@@ -118,6 +120,7 @@ DevParams dev_params(const tfan_params* p) {
   d.zeta = (float)p->zeta;
   d.h = (float)(1.0 / p->n_sub);
   d.rho0_d = p->rho0;
+  d.pop16 = p->storage == TFAN_STORAGE_F16;
   return d;
 }
 
@@ -213,11 +216,12 @@ int tfan_create(const tfan_params* p, void* ws, size_t bytes, void* stream, tfan
   tfan_sim* s = new tfan_sim();
   s->p = *p;
   s->dp = dev_params(p);
+  s->pop_bytes = p->storage == TFAN_STORAGE_F16 ? 2 : 4;
   s->stream = (hipStream_t)stream;
   (void)hipGetDevice(&s->device);
   char* base = (char*)ws;
   for (int k = 0; k < 2; ++k) {
-    s->f[k] = (float*)(base + L.f[k]);
+    s->f[k] = (void*)(base + L.f[k]);
     s->phi[k] = (float*)(base + L.phi[k]);
     s->q[k] = (float*)(base + L.q[k]);
   }
@@ -356,7 +360,7 @@ int tfan_diagnostics(tfan_sim* s, tfan_diag* out) {
 
 size_t tfan_state_bytes(const tfan_sim* s) {
   if (!s) return 0;
-  return sizeof(int64_t) + (size_t)s->dp.n * 21 * sizeof(float);
+  return sizeof(int64_t) + (size_t)s->dp.n * (18 * s->pop_bytes + 3 * sizeof(float));
 }
 
 int tfan_get_state(tfan_sim* s, void* host, size_t bytes) {
@@ -367,12 +371,12 @@ int tfan_get_state(tfan_sim* s, void* host, size_t bytes) {
   char* h = (char*)host;
   std::memcpy(h, &s->step, sizeof(int64_t));
   h += sizeof(int64_t);
-  hipError_t e = hipMemcpyAsync(h, s->f[s->cur], 18 * n * sizeof(float), hipMemcpyDeviceToHost, s->stream);
+  const size_t fb = 18 * n * s->pop_bytes;
+  hipError_t e = hipMemcpyAsync(h, s->f[s->cur], fb, hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h + 18 * n * sizeof(float), s->phi[s->cur], n * sizeof(float),
-                       hipMemcpyDeviceToHost, s->stream);
+    e = hipMemcpyAsync(h + fb, s->phi[s->cur], n * sizeof(float), hipMemcpyDeviceToHost, s->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h + 19 * n * sizeof(float), s->q[s->cur], 2 * n * sizeof(float),
+    e = hipMemcpyAsync(h + fb + n * sizeof(float), s->q[s->cur], 2 * n * sizeof(float),
                        hipMemcpyDeviceToHost, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "get_state");
   return sync_stream(s, "get_state");
@@ -389,13 +393,13 @@ int tfan_set_state(tfan_sim* s, const void* host, size_t bytes) {
   if (step < 0) return fail(s, TFAN_EINVAL, "negative step counter in state");
   h += sizeof(int64_t);
   s->cur = 0;
-  hipError_t e = hipMemcpyAsync(s->f[0], h, 18 * n * sizeof(float), hipMemcpyHostToDevice, s->stream);
+  const size_t fb = 18 * n * s->pop_bytes;
+  hipError_t e = hipMemcpyAsync(s->f[0], h, fb, hipMemcpyHostToDevice, s->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(s->phi[0], h + 18 * n * sizeof(float), n * sizeof(float), hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(s->phi[0], h + fb, n * sizeof(float), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->q[0], h + fb + n * sizeof(float), 2 * n * sizeof(float), hipMemcpyHostToDevice,
                        s->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(s->q[0], h + 19 * n * sizeof(float), 2 * n * sizeof(float),
-                       hipMemcpyHostToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state");
   s->step = step;
   return sync_stream(s, "set_state");

@@ -22,6 +22,7 @@ struct DevParams {
   float K, lam, Gamma, zeta;
   float h;             // 1 / n_sub
   double rho0_d;       // rho0 for float64 reductions
+  int pop16;           // populations stored as binary16 (else float32)
 };
 
 // Number of float64 slots in one diagnostics record.
@@ -34,7 +35,7 @@ enum DiagSlot {
 
 // Device buffers of one solver (all float32, each [ny][nx] plane n floats).
 struct DevState {
-  float* f;        // populations, shifted by -w_i rho0: [2 fluids][9][n]
+  void* f;         // populations, shifted by -w_i rho0: [2 fluids][9][n], float32 or binary16
   float* phi;      // [n]
   float* q;        // [2][n] (Qxx, Qxy)
 };
@@ -45,7 +46,7 @@ enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_COUNT };
 // Launchers (return hipGetLastError() after the launch).
 hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
                        hipStream_t st);
-hipError_t launch_collide(const DevParams& P, DevState in, float* f_out, float* u_out /*[4][n]*/,
+hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
                           hipStream_t st);
 // One finite-difference sub-step.
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,

@@ -16,6 +16,15 @@ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr float WT[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                          1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 
+// Population storage: float32, or IEEE binary16 of the same shifted values
+// (arithmetic is float32 either way; the conversion rounds to nearest even).
+template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, size_t i) {
+  return (float)static_cast<const PT*>(f)[i];
+}
+template <typename PT> __device__ __forceinline__ void pop_st(void* f, size_t i, float v) {
+  static_cast<PT*>(f)[i] = (PT)v;
+}
+
 // Periodic index for offsets |d| <= n.
 __device__ __forceinline__ int wrapi(int i, int n) {
   i = (i < 0) ? i + n : i;
@@ -68,9 +77,10 @@ __device__ __forceinline__ Stress nematic_stress(float qxx, float qxy, float qxx
 // BGK collision with the Guo source for one fluid, written post-collision:
 // f* = f + (f^eq - f)/tau + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F,
 // all populations shifted by -w_i rho0.
+template <typename PT>
 __device__ __forceinline__ void collide_fluid(const float f[9], float dr, float ux, float uy,
                                               float Fx, float Fy, float om, float gk, float rho0,
-                                              float* __restrict__ out, int n, int idx) {
+                                              void* __restrict__ out, size_t base, int n, int idx) {
   const float rho = rho0 + dr;
   const float uu15 = 1.5f * (ux * ux + uy * uy);
   const float uF = ux * Fx + uy * Fy;
@@ -80,7 +90,7 @@ __device__ __forceinline__ void collide_fluid(const float f[9], float dr, float 
     const float cF = (float)CX[i] * Fx + (float)CY[i] * Fy;
     const float feq = WT[i] * (dr + rho * (cu * (3.f + 4.5f * cu) - uu15));
     const float src = gk * WT[i] * (3.f * (cF - uF) + 9.f * cu * cF);
-    out[(size_t)i * n + idx] = f[i] + om * (feq - f[i]) + src;
+    pop_st<PT>(out, base + (size_t)i * n + idx, f[i] + om * (feq - f[i]) + src);
   }
 }
 
@@ -153,8 +163,8 @@ __device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, floa
   return make_float2(q.x + h * (advx + sxx + P.Gamma * hxx), q.y + h * (advy + sxy + P.Gamma * hxy));
 }
 
-template <bool FIELDS>
-__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, float* __restrict__ fout,
+template <bool FIELDS, typename PT>
+__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, void* __restrict__ fout,
                                                         float* __restrict__ uout) {
   __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
   __shared__ float smu[SY][SX], sxx[SY][SX], syy[SY][SX], ssy[SY][SX], san[SY][SX];
@@ -180,8 +190,8 @@ __global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in
     for (int i = 0; i < 9; ++i) {
       const int sx = (CX[i] == 0) ? xc : (CX[i] > 0 ? xm1 : xp1);
       const int sy = (CY[i] == 0) ? r0 : (CY[i] > 0 ? rm1 : rp1);
-      fa[s][i] = in.f[(size_t)i * n + sy + sx];
-      fp[s][i] = in.f[(size_t)(9 + i) * n + sy + sx];
+      fa[s][i] = pop_ld<PT>(in.f, (size_t)i * n + sy + sx);
+      fp[s][i] = pop_ld<PT>(in.f, (size_t)(9 + i) * n + sy + sx);
     }
   }
   // 2. stage phi, Qxx, Qxy on the tile with a halo of 2
@@ -255,9 +265,9 @@ __global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in
       uout[5 * n + idx] = upy;
     } else {
       const float fdx = 2.f * g * (upx - uax), fdy = 2.f * g * (upy - uay);
-      collide_fluid(fa[s], dra, uax, uay, Gax + fdx, Gay + fdy, P.om_a, P.gk_a, P.rho0, fout, n, idx);
-      collide_fluid(fp[s], drp, upx, upy, Gpx - fdx, Gpy - fdy, P.om_p, P.gk_p, P.rho0,
-                    fout + (size_t)9 * n, n, idx);
+      collide_fluid<PT>(fa[s], dra, uax, uay, Gax + fdx, Gay + fdy, P.om_a, P.gk_a, P.rho0, fout, 0, n, idx);
+      collide_fluid<PT>(fp[s], drp, upx, upy, Gpx - fdx, Gpy - fdy, P.om_p, P.gk_p, P.rho0, fout,
+                        (size_t)9 * n, n, idx);
       uout[idx] = uax;
       uout[n + idx] = uay;
       uout[2 * n + idx] = c1 * uax + c2 * upx;
@@ -354,8 +364,9 @@ __global__ void __launch_bounds__(FD_TX * FD_TY) k_fd(DevParams P, DevState in, 
 
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
 // stored f*_i(x) = f^eq_i(u(x + c_i)) - w_i rho0.
+template <typename PT>
 __global__ void __launch_bounds__(256) k_init(DevParams P, const float* __restrict__ aux,
-                                              float* __restrict__ f) {
+                                              void* __restrict__ f) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= P.nx || y >= P.ny) return;
@@ -368,8 +379,8 @@ __global__ void __launch_bounds__(256) k_init(DevParams P, const float* __restri
     for (int s = 0; s < 2; ++s) {
       const float ux = aux[(2 * s) * n + src], uy = aux[(2 * s + 1) * n + src];
       const float cu = (float)CX[i] * ux + (float)CY[i] * uy;
-      f[(size_t)(9 * s + i) * n + idx] =
-          WT[i] * P.rho0 * (cu * (3.f + 4.5f * cu) - 1.5f * (ux * ux + uy * uy));
+      pop_st<PT>(f, (size_t)(9 * s + i) * n + idx,
+                 WT[i] * P.rho0 * (cu * (3.f + 4.5f * cu) - 1.5f * (ux * ux + uy * uy)));
     }
   }
 }
@@ -412,6 +423,7 @@ __device__ __forceinline__ void block_reduce_store(double acc[kDiagSlots], doubl
 
 __device__ __forceinline__ int is_bad(float v) { return (isfinite(v) ? 0 : 1); }
 
+template <typename PT>
 __global__ void __launch_bounds__(kDiagThreads) k_diag(DevParams P, DevState in,
                                                       const float* __restrict__ aux,
                                                       double* __restrict__ partials) {
@@ -464,7 +476,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DevParams P, DevState in,
     acc[D_S] += sqrt(q1 * q1 + q2 * q2);
     int bad = is_bad(in.phi[idx]) + is_bad(qx[idx]) + is_bad(qy[idx]);
 #pragma unroll
-    for (int i = 0; i < 18; ++i) bad += is_bad(in.f[(size_t)i * n + idx]);
+    for (int i = 0; i < 18; ++i) bad += is_bad(pop_ld<PT>(in.f, (size_t)i * n + idx));
     acc[D_NONFINITE] += (double)bad;
   }
   block_reduce_store(acc, partials + (size_t)blockIdx.x * kDiagSlots);
@@ -498,7 +510,10 @@ int diag_blocks(const DevParams& P) {
 
 hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hipStream_t st) {
   const dim3 blk(64, 4);
-  hipLaunchKernelGGL(k_init, grid2d(P, blk), blk, 0, st, P, aux_u, out.f);
+  if (P.pop16)
+    hipLaunchKernelGGL(k_init<_Float16>, grid2d(P, blk), blk, 0, st, P, aux_u, out.f);
+  else
+    hipLaunchKernelGGL(k_init<float>, grid2d(P, blk), blk, 0, st, P, aux_u, out.f);
   return hipGetLastError();
 }
 
@@ -506,9 +521,12 @@ inline int collide_tiles(const DevParams& P) {
   return ((P.nx + CT_X - 1) / CT_X) * ((P.ny + CT_Y - 1) / CT_Y);
 }
 
-hipError_t launch_collide(const DevParams& P, DevState in, float* f_out, float* u_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_collide<false>, dim3(xcd_grid(collide_tiles(P))), dim3(CT_THREADS), 0, st, P, in,
-                     f_out, u_out);
+hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out, hipStream_t st) {
+  const dim3 grid(xcd_grid(collide_tiles(P)));
+  if (P.pop16)
+    hipLaunchKernelGGL((k_collide<false, _Float16>), grid, dim3(CT_THREADS), 0, st, P, in, f_out, u_out);
+  else
+    hipLaunchKernelGGL((k_collide<false, float>), grid, dim3(CT_THREADS), 0, st, P, in, f_out, u_out);
   return hipGetLastError();
 }
 
@@ -519,14 +537,20 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
 }
 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
-  hipLaunchKernelGGL(k_collide<true>, dim3(xcd_grid(collide_tiles(P))), dim3(CT_THREADS), 0, st, P, in,
-                     nullptr, aux);
+  const dim3 grid(xcd_grid(collide_tiles(P)));
+  if (P.pop16)
+    hipLaunchKernelGGL((k_collide<true, _Float16>), grid, dim3(CT_THREADS), 0, st, P, in, nullptr, aux);
+  else
+    hipLaunchKernelGGL((k_collide<true, float>), grid, dim3(CT_THREADS), 0, st, P, in, nullptr, aux);
   return hipGetLastError();
 }
 
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux, double* partials,
                        int nblocks, double* result, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag, dim3(nblocks), dim3(kDiagThreads), 0, st, P, in, aux, partials);
+  if (P.pop16)
+    hipLaunchKernelGGL(k_diag<_Float16>, dim3(nblocks), dim3(kDiagThreads), 0, st, P, in, aux, partials);
+  else
+    hipLaunchKernelGGL(k_diag<float>, dim3(nblocks), dim3(kDiagThreads), 0, st, P, in, aux, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, st, partials, nblocks, result);

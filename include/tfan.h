@@ -158,12 +158,52 @@ int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n);
 int tfan_kernel_count(void);
 const char* tfan_kernel_name(int id);
 
+/* Launch shape of the two hot kernels: collide_rows in {1, 2} rows of sites per
+ * thread of the collision kernel, fd_rows in {1, 2, 4} of the sub-step kernel.
+ * Results are bitwise identical for every shape; only the speed differs. */
+int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_rows);
+int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_rows);
+
+/* Autotuner: runs `steps` steps (after one warm-up step) with every launch
+ * shape, keeps the fastest, restores the state it started from (checkpoint
+ * through host memory) and reports the best time per step (may be NULL). */
+int tfan_autotune(tfan_sim* s, int32_t steps, double* best_ms_per_step);
+
 /* Release the handle (never the workspace). NULL is ignored. */
 void tfan_destroy(tfan_sim* s);
 
 /* Message of the last failure on s; s = NULL gives the last failure of a call
  * without a valid handle (check_params, create). */
 const char* tfan_last_error(const tfan_sim* s);
+
+/* ------------------------------------------------------------------------
+ * Batches of independent simulations (parameter sweeps).  Each member has its
+ * own grid and parameters; all members share n_sub and the storage format.
+ * tfan_batch_step advances every member by one collision launch and one launch
+ * per sub-step over the tiles of all members, so small grids fill the GPU
+ * together.  p points to `count` parameter blocks; the workspace holds every
+ * member's state plus a small device table.  Member indices are 0..count-1.
+ * Results of a member are bitwise identical to a single simulation with the
+ * same parameters and launch shape.
+ * ---------------------------------------------------------------------- */
+typedef struct tfan_batch tfan_batch;
+
+size_t tfan_batch_workspace_bytes(const tfan_params* p, int32_t count);   /* 0 if invalid */
+int tfan_batch_create(const tfan_params* p, int32_t count, void* dev_workspace, size_t bytes,
+                      void* hip_stream, tfan_batch** out);
+int tfan_batch_count(const tfan_batch* b);
+int tfan_batch_init_fields(tfan_batch* b, int32_t member, const double* phi, const double* qxx,
+                           const double* qxy, const double* u_a, const double* u_p);
+int tfan_batch_step(tfan_batch* b, int64_t n);                           /* async */
+int tfan_batch_get_fields(tfan_batch* b, int32_t member, double* phi, double* qxx, double* qxy,
+                          double* u_a, double* u_p, double* rho_a, double* rho_p);
+int tfan_batch_diagnostics(tfan_batch* b, int32_t member, tfan_diag* out);
+int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_rows);
+int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_rows);
+int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step);
+int tfan_batch_sync(tfan_batch* b);
+void tfan_batch_destroy(tfan_batch* b);
+const char* tfan_batch_last_error(const tfan_batch* b);
 
 #ifdef __cplusplus
 }

@@ -77,6 +77,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int64]),
         "tfan_kernel_times": (ctypes.c_int, [_vp, _dp, _P(ctypes.c_int64), ctypes.c_int]),
         "tfan_kernel_count": (ctypes.c_int, []),
+        "tfan_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "tfan_get_tuning": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+        "tfan_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+        "tfan_batch_workspace_bytes": (ctypes.c_size_t, [_P(tfan_params), ctypes.c_int32]),
+        "tfan_batch_create": (ctypes.c_int, [_P(tfan_params), ctypes.c_int32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+        "tfan_batch_count": (ctypes.c_int, [_vp]),
+        "tfan_batch_init_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp]),
+        "tfan_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "tfan_batch_get_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+        "tfan_batch_diagnostics": (ctypes.c_int, [_vp, ctypes.c_int32, _P(tfan_diag)]),
+        "tfan_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+        "tfan_batch_get_tuning": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+        "tfan_batch_autotune": (ctypes.c_int, [_vp, ctypes.c_int32, _dp]),
+        "tfan_batch_sync": (ctypes.c_int, [_vp]),
+        "tfan_batch_destroy": (None, [_vp]),
+        "tfan_batch_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
         "tfan_destroy": (None, [_vp]),
         "tfan_last_error": (ctypes.c_char_p, [_vp]),
@@ -210,6 +226,19 @@ class Sim:
     def kernel_timing(self, cap: int):
         self._check(self.lib.tfan_kernel_timing(self._handle, int(cap)))
 
+    def set_tuning(self, collide_rows: int, fd_rows: int):
+        self._check(self.lib.tfan_set_tuning(self._handle, int(collide_rows), int(fd_rows)))
+
+    def get_tuning(self) -> tuple:
+        c, f = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.tfan_get_tuning(self._handle, ctypes.byref(c), ctypes.byref(f)))
+        return c.value, f.value
+
+    def autotune(self, steps: int = 20) -> float:
+        ms = ctypes.c_double()
+        self._check(self.lib.tfan_autotune(self._handle, int(steps), ctypes.byref(ms)))
+        return ms.value
+
     def kernel_times(self) -> dict:
         k = int(self.lib.tfan_kernel_count())
         ms = (ctypes.c_double * k)()
@@ -220,6 +249,101 @@ class Sim:
     def close(self):
         if getattr(self, "_handle", None) and self._handle.value:
             self.lib.tfan_destroy(self._handle)
+            self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent simulations advanced together (one launch per phase for all)."""
+
+    def __init__(self, params_list, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the solver runs only on the GPU")
+        self.lib = load_library()
+        self.params = [dict(p) for p in params_list]
+        arr = (tfan_params * len(self.params))(*[make_params(p) for p in self.params])
+        nbytes = int(self.lib.tfan_batch_workspace_bytes(arr, len(self.params)))
+        if nbytes == 0:
+            for p in self.params:
+                check_params(p)
+            raise TfanError(TFAN_EINVAL, "invalid batch")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self._handle = _vp()
+        with torch.cuda.device(self.device):
+            rc = self.lib.tfan_batch_create(arr, len(self.params), _vp(aligned), nbytes,
+                                            _vp(self.stream.cuda_stream), ctypes.byref(self._handle))
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_batch_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_batch_last_error(self._handle).decode())
+
+    def __len__(self):
+        return len(self.params)
+
+    def _member(self, member):
+        if not 0 <= int(member) < len(self.params):
+            raise TfanError(TFAN_EINVAL, f"member {member} out of range")
+        return self.params[int(member)]
+
+    def init_fields(self, member, phi, qxx, qxy, u_a=None, u_p=None):
+        p = self._member(member)
+        s = (int(p["ny"]), int(p["nx"]))
+        arrs = [_f64(phi, s), _f64(qxx, s), _f64(qxy, s), _f64(u_a, (2,) + s), _f64(u_p, (2,) + s)]
+        self._check(self.lib.tfan_batch_init_fields(self._handle, int(member), *[_ptr(a) for a in arrs]))
+
+    def step(self, n: int = 1):
+        self._check(self.lib.tfan_batch_step(self._handle, int(n)))
+
+    def get_fields(self, member) -> dict:
+        p = self._member(member)
+        s = (int(p["ny"]), int(p["nx"]))
+        out = dict(phi=np.empty(s), qxx=np.empty(s), qxy=np.empty(s), u_a=np.empty((2,) + s),
+                   u_p=np.empty((2,) + s), rho_a=np.empty(s), rho_p=np.empty(s))
+        self._check(self.lib.tfan_batch_get_fields(self._handle, int(member), *[
+            _ptr(out[k]) for k in ("phi", "qxx", "qxy", "u_a", "u_p", "rho_a", "rho_p")]))
+        return out
+
+    def diagnostics(self, member) -> dict:
+        d = tfan_diag()
+        rc = self.lib.tfan_batch_diagnostics(self._handle, int(member), ctypes.byref(d))
+        if rc not in (TFAN_OK, TFAN_ENONFINITE, TFAN_EUNSTABLE):
+            self._check(rc)
+        out = {name: getattr(d, name) for name, _ in tfan_diag._fields_}
+        out["status"] = rc
+        return out
+
+    def set_tuning(self, collide_rows: int, fd_rows: int):
+        self._check(self.lib.tfan_batch_set_tuning(self._handle, int(collide_rows), int(fd_rows)))
+
+    def get_tuning(self) -> tuple:
+        c, f = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.tfan_batch_get_tuning(self._handle, ctypes.byref(c), ctypes.byref(f)))
+        return c.value, f.value
+
+    def autotune(self, steps: int = 10) -> float:
+        ms = ctypes.c_double()
+        self._check(self.lib.tfan_batch_autotune(self._handle, int(steps), ctypes.byref(ms)))
+        return ms.value
+
+    def sync(self):
+        self._check(self.lib.tfan_batch_sync(self._handle))
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            self.lib.tfan_batch_destroy(self._handle)
             self._handle = _vp()
 
     def __del__(self):

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are kept out of the generated code.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-             "-ffp-contract=fast", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
+             "-ffp-contract=on", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 SOURCES = ["tfan.cpp", "tfan_kernels.hip"]
 
 

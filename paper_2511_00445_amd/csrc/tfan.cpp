@@ -29,6 +29,7 @@ struct tfan_sim {
   double* partials = nullptr;          // [diag blocks][kDiagSlots]
   double* result = nullptr;            // [kDiagSlots]
   int cur = 0;                         // index of the buffers holding the state
+  tfan::Tuning tune;                   // launch shape of the hot kernels
   int64_t step = 0;
   std::string err;
   // kernel timing
@@ -271,14 +272,14 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
     const int a = s->cur, b = 1 - s->cur;
     {
       TimedLaunch t(s, tfan::K_COLLIDE);
-      hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->stream);
+      hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->tune, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "collide kernel launch");
     }
     // sub-steps alternate the phi/Q buffers; the collision above already read state a
     int src = a;
     for (int m = 0; m < s->dp.n_sub; ++m) {
       TimedLaunch t(s, tfan::K_FD);
-      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->stream);
+      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
       src = 1 - src;
     }
@@ -448,6 +449,61 @@ int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n) {
   return TFAN_OK;
 }
 
+int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_rows) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if ((collide_rows != 1 && collide_rows != 2) || (fd_rows != 1 && fd_rows != 2 && fd_rows != 4))
+    return fail(s, TFAN_EINVAL, "collide_rows must be 1 or 2 and fd_rows 1, 2 or 4");
+  s->tune.collide_rows = collide_rows;
+  s->tune.fd_rows = fd_rows;
+  return TFAN_OK;
+}
+
+int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_rows) {
+  if (!s || !collide_rows || !fd_rows) return fail(nullptr, TFAN_EINVAL, "NULL argument");
+  *collide_rows = s->tune.collide_rows;
+  *fd_rows = s->tune.fd_rows;
+  return TFAN_OK;
+}
+
+int tfan_autotune(tfan_sim* s, int32_t steps, double* best_ms_per_step) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (steps < 1 || steps > 100000) return fail(s, TFAN_EINVAL, "steps must be in [1, 100000]");
+  std::vector<unsigned char> ck(tfan_state_bytes(s));
+  int rc = tfan_get_state(s, ck.data(), ck.size());
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(s, e, "autotune events");
+  const int crows[2] = {1, 2}, frows[3] = {1, 2, 4};
+  tfan::Tuning best = s->tune;
+  float best_ms = -1.f;
+  for (int c : crows)
+    for (int f : frows) {
+      s->tune.collide_rows = c;
+      s->tune.fd_rows = f;
+      if ((rc = tfan_step(s, 1))) break;  // warm-up
+      (void)hipEventRecord(e0, s->stream);
+      if ((rc = tfan_step(s, steps))) break;
+      (void)hipEventRecord(e1, s->stream);
+      if ((rc = sync_stream(s, "autotune"))) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms < 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = s->tune;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tune = best;
+  const int rc2 = tfan_set_state(s, ck.data(), ck.size());
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (best_ms_per_step) *best_ms_per_step = best_ms / steps;
+  return TFAN_OK;
+}
+
 int tfan_kernel_count(void) { return tfan::K_COUNT; }
 
 const char* tfan_kernel_name(int id) {
@@ -463,5 +519,291 @@ void tfan_destroy(tfan_sim* s) {
 }
 
 const char* tfan_last_error(const tfan_sim* s) { return s ? s->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: independent members with their own grids and parameters (equal
+// n_sub and storage), advanced together by one collision launch and one launch
+// per sub-step over the tiles of all members.
+// ---------------------------------------------------------------------------
+struct tfan_batch {
+  std::vector<tfan_sim*> m;
+  hipStream_t stream = nullptr;
+  tfan::BatchMember* table = nullptr;  // device
+  int* first_c = nullptr;              // device [count]
+  int* first_f = nullptr;              // device [count]
+  int tiles_c = 0, tiles_f = 0;
+  int cur = 0;
+  int64_t step = 0;
+  tfan::Tuning tune;
+  bool pop16 = false;
+  int n_sub = 0;
+  std::string err;
+};
+
+namespace {
+
+int bfail(tfan_batch* b, int code, const std::string& msg) {
+  if (b) b->err = msg; else g_err = msg;
+  return code;
+}
+
+size_t batch_table_bytes(int count) {
+  return align_up(count * sizeof(tfan::BatchMember)) + 2 * align_up(count * sizeof(int));
+}
+
+int upload_first(tfan_batch* b) {
+  std::vector<int> fc(b->m.size()), ff(b->m.size());
+  int tc = 0, tf = 0;
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    fc[i] = tc;
+    ff[i] = tf;
+    tc += tfan::batch_tiles(b->m[i]->dp, b->tune, true);
+    tf += tfan::batch_tiles(b->m[i]->dp, b->tune, false);
+  }
+  b->tiles_c = tc;
+  b->tiles_f = tf;
+  hipError_t e = hipMemcpyAsync(b->first_c, fc.data(), fc.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->first_f, ff.data(), ff.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch tables: ") + hipGetErrorString(e));
+  return TFAN_OK;
+}
+
+int member_check(tfan_batch* b, int32_t member) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  if (member < 0 || member >= (int32_t)b->m.size()) return bfail(b, TFAN_EINVAL, "member out of range");
+  return TFAN_OK;
+}
+
+// A member re-initialised (state in buffer 0) while the batch holds its state in
+// buffer 1: copy it across so that all members share one ping-pong index.
+int align_member(tfan_batch* b, tfan_sim* s) {
+  if (s->cur == b->cur) return TFAN_OK;
+  const size_t n = (size_t)s->dp.n;
+  hipError_t e = hipMemcpyAsync(s->f[b->cur], s->f[s->cur], 18 * n * s->pop_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->phi[b->cur], s->phi[s->cur], n * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->q[b->cur], s->q[s->cur], 2 * n * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch align: ") + hipGetErrorString(e));
+  s->cur = b->cur;
+  return TFAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tfan_batch_workspace_bytes(const tfan_params* p, int32_t count) {
+  if (!p || count < 1 || count > 4096) return 0;
+  size_t total = batch_table_bytes(count);
+  for (int i = 0; i < count; ++i) {
+    const size_t w = tfan_workspace_bytes(p + i);
+    if (!w) return 0;
+    total += align_up(w);
+  }
+  return total;
+}
+
+int tfan_batch_create(const tfan_params* p, int32_t count, void* ws, size_t bytes, void* stream,
+                      tfan_batch** out) {
+  if (!out) return bfail(nullptr, TFAN_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || count < 1 || count > 4096) return bfail(nullptr, TFAN_EINVAL, "count must be in [1, 4096]");
+  for (int i = 0; i < count; ++i) {
+    const std::string m = check(p + i);
+    if (!m.empty()) return bfail(nullptr, TFAN_EINVAL, "member " + std::to_string(i) + ": " + m);
+    if (p[i].n_sub != p[0].n_sub || p[i].storage != p[0].storage)
+      return bfail(nullptr, TFAN_EINVAL, "all members need the same n_sub and storage");
+  }
+  const size_t need = tfan_batch_workspace_bytes(p, count);
+  if (!ws) return bfail(nullptr, TFAN_EINVAL, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return bfail(nullptr, TFAN_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < need) return bfail(nullptr, TFAN_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  tfan_batch* b = new tfan_batch();
+  b->stream = (hipStream_t)stream;
+  char* base = (char*)ws;
+  b->table = (tfan::BatchMember*)base;
+  b->first_c = (int*)(base + align_up(count * sizeof(tfan::BatchMember)));
+  b->first_f = (int*)((char*)b->first_c + align_up(count * sizeof(int)));
+  size_t off = batch_table_bytes(count);
+  std::vector<tfan::BatchMember> host(count);
+  for (int i = 0; i < count; ++i) {
+    const size_t w = tfan_workspace_bytes(p + i);
+    tfan_sim* s = nullptr;
+    int rc = tfan_create(p + i, base + off, w, stream, &s);
+    if (rc) {
+      for (tfan_sim* t : b->m) tfan_destroy(t);
+      delete b;
+      return rc;
+    }
+    off += align_up(w);
+    b->m.push_back(s);
+    host[i].P = s->dp;
+    host[i].st[0] = state_of(s, 0);
+    host[i].st[1] = state_of(s, 1);
+    host[i].U = s->U;
+  }
+  b->pop16 = p[0].storage == TFAN_STORAGE_F16;
+  b->n_sub = p[0].n_sub;
+  hipError_t e = hipMemcpyAsync(b->table, host.data(), count * sizeof(tfan::BatchMember), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  int rc = e == hipSuccess ? upload_first(b) : bfail(b, TFAN_EHIP, hipGetErrorString(e));
+  if (rc) {
+    g_err = b->err;
+    for (tfan_sim* t : b->m) tfan_destroy(t);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return TFAN_OK;
+}
+
+int tfan_batch_count(const tfan_batch* b) { return b ? (int)b->m.size() : -1; }
+
+int tfan_batch_init_fields(tfan_batch* b, int32_t member, const double* phi, const double* qxx,
+                           const double* qxy, const double* u_a, const double* u_p) {
+  int rc = member_check(b, member);
+  if (rc) return rc;
+  tfan_sim* s = b->m[member];
+  rc = tfan_init_fields(s, phi, qxx, qxy, u_a, u_p);
+  if (rc) return bfail(b, rc, s->err);
+  return align_member(b, s);
+}
+
+int tfan_batch_step(tfan_batch* b, int64_t nsteps) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  if (nsteps < 0) return bfail(b, TFAN_EINVAL, "step count must be >= 0");
+  const int count = (int)b->m.size();
+  for (int64_t k = 0; k < nsteps; ++k) {
+    hipError_t e = tfan::launch_collide_batch(b->table, b->first_c, count, b->tiles_c, b->cur, b->pop16, b->tune,
+                                              b->stream);
+    if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch collide launch: ") + hipGetErrorString(e));
+    int src = b->cur;
+    for (int m = 0; m < b->n_sub; ++m) {
+      e = tfan::launch_fd_batch(b->table, b->first_f, count, b->tiles_f, src, b->tune, b->stream);
+      if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch sub-step launch: ") + hipGetErrorString(e));
+      src = 1 - src;
+    }
+    const int nb = 1 - b->cur;
+    if (src != nb) {
+      for (tfan_sim* s : b->m) {
+        const size_t n = (size_t)s->dp.n;
+        e = hipMemcpyAsync(s->phi[nb], s->phi[src], n * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(s->q[nb], s->q[src], 2 * n * sizeof(float), hipMemcpyDeviceToDevice, b->stream);
+        if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch field copy: ") + hipGetErrorString(e));
+      }
+    }
+    b->cur = nb;
+    b->step += 1;
+    for (tfan_sim* s : b->m) {
+      s->cur = nb;
+      s->step += 1;
+    }
+  }
+  return TFAN_OK;
+}
+
+int tfan_batch_get_fields(tfan_batch* b, int32_t member, double* phi, double* qxx, double* qxy, double* u_a,
+                          double* u_p, double* rho_a, double* rho_p) {
+  int rc = member_check(b, member);
+  if (rc) return rc;
+  rc = tfan_get_fields(b->m[member], phi, qxx, qxy, u_a, u_p, rho_a, rho_p);
+  return rc ? bfail(b, rc, b->m[member]->err) : TFAN_OK;
+}
+
+int tfan_batch_diagnostics(tfan_batch* b, int32_t member, tfan_diag* out) {
+  int rc = member_check(b, member);
+  if (rc) return rc;
+  rc = tfan_diagnostics(b->m[member], out);
+  if (rc) b->err = b->m[member]->err;
+  return rc;
+}
+
+int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_rows) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  if ((collide_rows != 1 && collide_rows != 2) || (fd_rows != 1 && fd_rows != 2 && fd_rows != 4))
+    return bfail(b, TFAN_EINVAL, "collide_rows must be 1 or 2 and fd_rows 1, 2 or 4");
+  b->tune.collide_rows = collide_rows;
+  b->tune.fd_rows = fd_rows;
+  return upload_first(b);
+}
+
+int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_rows) {
+  if (!b || !collide_rows || !fd_rows) return bfail(nullptr, TFAN_EINVAL, "NULL argument");
+  *collide_rows = b->tune.collide_rows;
+  *fd_rows = b->tune.fd_rows;
+  return TFAN_OK;
+}
+
+int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  if (steps < 1 || steps > 100000) return bfail(b, TFAN_EINVAL, "steps must be in [1, 100000]");
+  std::vector<std::vector<unsigned char>> ck(b->m.size());
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    ck[i].resize(tfan_state_bytes(b->m[i]));
+    int rc = tfan_get_state(b->m[i], ck[i].data(), ck[i].size());
+    if (rc) return bfail(b, rc, b->m[i]->err);
+  }
+  const int64_t step0 = b->step;
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return bfail(b, TFAN_EHIP, "autotune events");
+  const int crows[2] = {1, 2}, frows[3] = {1, 2, 4};
+  tfan::Tuning best = b->tune;
+  float best_ms = -1.f;
+  int rc = TFAN_OK;
+  for (int c : crows)
+    for (int f : frows) {
+      if ((rc = tfan_batch_set_tuning(b, c, f))) break;
+      if ((rc = tfan_batch_step(b, 1))) break;
+      (void)hipEventRecord(e0, b->stream);
+      if ((rc = tfan_batch_step(b, steps))) break;
+      (void)hipEventRecord(e1, b->stream);
+      if (hipStreamSynchronize(b->stream) != hipSuccess) { rc = bfail(b, TFAN_EHIP, "autotune sync"); break; }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best_ms < 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = b->tune;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // restore: every member back to its checkpoint, in buffer 0
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    const int r2 = tfan_set_state(b->m[i], ck[i].data(), ck[i].size());
+    if (r2 && !rc) rc = bfail(b, r2, b->m[i]->err);
+  }
+  b->cur = 0;
+  b->step = step0;
+  const int r3 = tfan_batch_set_tuning(b, best.collide_rows, best.fd_rows);
+  if (rc) return rc;
+  if (r3) return r3;
+  if (best_ms_per_step) *best_ms_per_step = best_ms / steps;
+  return TFAN_OK;
+}
+
+int tfan_batch_sync(tfan_batch* b) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  return e == hipSuccess ? TFAN_OK : bfail(b, TFAN_EHIP, std::string("batch sync: ") + hipGetErrorString(e));
+}
+
+void tfan_batch_destroy(tfan_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  for (tfan_sim* s : b->m) tfan_destroy(s);
+  delete b;
+}
+
+const char* tfan_batch_last_error(const tfan_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"

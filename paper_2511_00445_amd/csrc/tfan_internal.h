@@ -40,6 +40,20 @@ struct DevState {
   float* q;        // [2][n] (Qxx, Qxy)
 };
 
+// Launch shape of the two hot kernels (results do not depend on it):
+// collide_rows in {1, 2} rows of sites per thread, fd_rows in {1, 2, 4}.
+struct Tuning {
+  int collide_rows = 2;
+  int fd_rows = 4;
+};
+
+// One member of a batch of independent simulations (device-resident table).
+struct BatchMember {
+  DevParams P;
+  DevState st[2];  // ping-pong states
+  float* U;        // frozen velocities [4][n]
+};
+
 // Kernel ids for timing.
 enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_COUNT };
 
@@ -47,10 +61,17 @@ enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_COUNT };
 hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
                        hipStream_t st);
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
-                          hipStream_t st);
+                          Tuning tn, hipStream_t st);
 // One finite-difference sub-step.
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
-                     hipStream_t st);
+                     Tuning tn, hipStream_t st);
+// Tiles of one member for the collision (collide = true) or sub-step kernel.
+int batch_tiles(const DevParams& P, Tuning tn, bool collide);
+// Batched launches over the tiles of all members; first[m] = first tile of member m.
+hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur,
+                                bool pop16, Tuning tn, hipStream_t st);
+hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src,
+                           Tuning tn, hipStream_t st);
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: drho_a, drho_p, u_a, u_p*/,
                          hipStream_t st);
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,

@@ -21,8 +21,11 @@ constexpr float WT[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
 template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, size_t i) {
   return (float)static_cast<const PT*>(f)[i];
 }
+// Populations are written with a non-temporal hint: they are not read again
+// until the next step, and keeping them out of the caches leaves phi, Q and the
+// frozen velocities resident for the sub-step passes that follow.
 template <typename PT> __device__ __forceinline__ void pop_st(void* f, size_t i, float v) {
-  static_cast<PT*>(f)[i] = (PT)v;
+  __builtin_nontemporal_store((PT)v, static_cast<PT*>(f) + i);
 }
 
 // Periodic index for offsets |d| <= n.
@@ -102,11 +105,9 @@ __device__ __forceinline__ void collide_fluid(const float f[9], float dr, float 
 // behind it.  FIELDS = true evaluates the same velocities and densities and
 // writes them out instead of colliding (get_fields / diagnostics).
 // ---------------------------------------------------------------------------
-constexpr int CT_X = 64, CT_Y = 8, CT_THREADS = 256;
-constexpr int CT_ROWS_PER_PASS = CT_THREADS / CT_X;  // 4
-constexpr int CT_SITES = CT_Y / CT_ROWS_PER_PASS;    // 2 sites per thread
-constexpr int PX = CT_X + 4, PY = CT_Y + 4;          // phi/Q staging, halo 2
-constexpr int SX = CT_X + 2, SY = CT_Y + 2;          // mu/stress region, halo 1
+constexpr int CT_X = 64, CT_THREADS = 256;
+constexpr int CT_ROWS_PER_PASS = CT_THREADS / CT_X;  // 4 rows per pass of the block
+constexpr int PX = CT_X + 4, SX = CT_X + 2;          // phi/Q staging halo 2, mu/stress halo 1
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Launching 8 * ceil(tiles / 8) workgroups and giving XCD k the contiguous tile
@@ -163,15 +164,19 @@ __device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, floa
   return make_float2(q.x + h * (advx + sxx + P.Gamma * hxx), q.y + h * (advy + sxy + P.Gamma * hxy));
 }
 
-template <bool FIELDS, typename PT>
-__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, void* __restrict__ fout,
-                                                        float* __restrict__ uout) {
+// Tiles of the collision kernel: CT_X x (4 * SITES) sites, SITES rows per thread.
+template <int SITES> __host__ __device__ inline int collide_tiles(int nx, int ny) {
+  return ((nx + CT_X - 1) / CT_X) * ((ny + CT_ROWS_PER_PASS * SITES - 1) / (CT_ROWS_PER_PASS * SITES));
+}
+
+template <bool FIELDS, typename PT, int CT_SITES>
+__device__ __forceinline__ void collide_tile(const DevParams& P, const DevState& in, void* __restrict__ fout,
+                                             float* __restrict__ uout, int tile) {
+  constexpr int CT_Y = CT_ROWS_PER_PASS * CT_SITES, PY = CT_Y + 4, SY = CT_Y + 2;
   __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
   __shared__ float smu[SY][SX], sxx[SY][SX], syy[SY][SX], ssy[SY][SX], san[SY][SX];
   const int nx = P.nx, ny = P.ny, n = P.n;
   const int gx = (nx + CT_X - 1) / CT_X;
-  const int tile = xcd_tile(gx * ((ny + CT_Y - 1) / CT_Y));
-  if (tile < 0) return;  // whole workgroup, before any barrier
   const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
   const int x0 = (tile % gx) * CT_X, y0 = (tile / gx) * CT_Y;
 
@@ -276,24 +281,52 @@ __global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in
   }
 }
 
+template <bool FIELDS, typename PT, int SITES>
+__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, void* __restrict__ fout,
+                                                        float* __restrict__ uout) {
+  const int tile = xcd_tile(collide_tiles<SITES>(P.nx, P.ny));
+  if (tile < 0) return;  // whole workgroup, before any barrier
+  collide_tile<FIELDS, PT, SITES>(P, in, fout, uout, tile);
+}
+
+// Member of a batch whose tile index range starts at `first` (ascending array).
+__device__ __forceinline__ int batch_member(const int* __restrict__ first, int count, int tile) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename PT, int SITES>
+__global__ void __launch_bounds__(CT_THREADS) k_collide_batch(const BatchMember* __restrict__ mem,
+                                                              const int* __restrict__ first, int count,
+                                                              int tiles, int cur) {
+  const int tile = xcd_tile(tiles);
+  if (tile < 0) return;
+  const int m = batch_member(first, count, tile);
+  const DevParams P = mem[m].P;
+  const DevState in = mem[m].st[cur];
+  collide_tile<false, PT, SITES>(P, in, mem[m].st[1 - cur].f, mem[m].U, tile - first[m]);
+}
+
 // ---------------------------------------------------------------------------
 // One forward-Euler sub-step of the Cahn-Hilliard (Model, Eq. 1) and
 // Beris-Edwards (Model, Eqs. 11-12) equations with u_a and u_c frozen.  Each
 // thread updates R consecutive rows of one column, so the stencils of
 // neighbouring rows share their loads and their chemical-potential values.
 // ---------------------------------------------------------------------------
-#ifndef TFAN_FD_R
-#define TFAN_FD_R 4
-#endif
-constexpr int FD_TX = 64, FD_TY = 4, FD_R = TFAN_FD_R;
+constexpr int FD_TX = 64, FD_TY = 4;
+template <int R> __host__ __device__ inline int fd_tiles(int nx, int ny) {
+  return ((nx + FD_TX - 1) / FD_TX) * ((ny + FD_TY * R - 1) / (FD_TY * R));
+}
 
 template <int R>
-__global__ void __launch_bounds__(FD_TX * FD_TY) k_fd(DevParams P, DevState in, DevState out,
-                                                       const float* __restrict__ U) {
+__device__ __forceinline__ void fd_tile(const DevParams& P, const DevState& in, const DevState& out,
+                                        const float* __restrict__ U, int tile) {
   const int nx = P.nx, ny = P.ny, n = P.n;
   const int gx = (nx + FD_TX - 1) / FD_TX;
-  const int tile = xcd_tile(gx * ((ny + FD_TY * R - 1) / (FD_TY * R)));
-  if (tile < 0) return;
   const int x = (tile % gx) * FD_TX + threadIdx.x;
   const int y0 = ((tile / gx) * FD_TY + threadIdx.y) * R;
   if (x >= nx || y0 >= ny) return;
@@ -360,6 +393,25 @@ __global__ void __launch_bounds__(FD_TX * FD_TY) k_fd(DevParams P, DevState in, 
     stg(oqx, o, nq.x);
     stg(oqy, o, nq.y);
   }
+}
+
+template <int R>
+__global__ void __launch_bounds__(FD_TX * FD_TY) k_fd(DevParams P, DevState in, DevState out,
+                                                       const float* __restrict__ U) {
+  const int tile = xcd_tile(fd_tiles<R>(P.nx, P.ny));
+  if (tile < 0) return;
+  fd_tile<R>(P, in, out, U, tile);
+}
+
+template <int R>
+__global__ void __launch_bounds__(FD_TX * FD_TY) k_fd_batch(const BatchMember* __restrict__ mem,
+                                                             const int* __restrict__ first, int count,
+                                                             int tiles, int src) {
+  const int tile = xcd_tile(tiles);
+  if (tile < 0) return;
+  const int m = batch_member(first, count, tile);
+  const DevParams P = mem[m].P;
+  fd_tile<R>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m]);
 }
 
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
@@ -517,31 +569,68 @@ hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hip
   return hipGetLastError();
 }
 
-inline int collide_tiles(const DevParams& P) {
-  return ((P.nx + CT_X - 1) / CT_X) * ((P.ny + CT_Y - 1) / CT_Y);
-}
+#define TFAN_POP_DISPATCH(KERNEL_F32, KERNEL_F16, ...)                        \
+  do {                                                                     \
+    if (P.pop16) hipLaunchKernelGGL(KERNEL_F16, __VA_ARGS__);                \
+    else hipLaunchKernelGGL(KERNEL_F32, __VA_ARGS__);                        \
+  } while (0)
 
-hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out, hipStream_t st) {
-  const dim3 grid(xcd_grid(collide_tiles(P)));
-  if (P.pop16)
-    hipLaunchKernelGGL((k_collide<false, _Float16>), grid, dim3(CT_THREADS), 0, st, P, in, f_out, u_out);
-  else
-    hipLaunchKernelGGL((k_collide<false, float>), grid, dim3(CT_THREADS), 0, st, P, in, f_out, u_out);
+hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out, Tuning tn,
+                          hipStream_t st) {
+  if (tn.collide_rows == 1) {
+    const dim3 grid(xcd_grid(collide_tiles<1>(P.nx, P.ny)));
+    TFAN_POP_DISPATCH((k_collide<false, float, 1>), (k_collide<false, _Float16, 1>), grid, dim3(CT_THREADS), 0, st,
+                      P, in, f_out, u_out);
+  } else {
+    const dim3 grid(xcd_grid(collide_tiles<2>(P.nx, P.ny)));
+    TFAN_POP_DISPATCH((k_collide<false, float, 2>), (k_collide<false, _Float16, 2>), grid, dim3(CT_THREADS), 0, st,
+                      P, in, f_out, u_out);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, hipStream_t st) {
-  const int tiles = ((P.nx + FD_TX - 1) / FD_TX) * ((P.ny + FD_TY * FD_R - 1) / (FD_TY * FD_R));
-  hipLaunchKernelGGL(k_fd<FD_R>, dim3(xcd_grid(tiles)), dim3(FD_TX, FD_TY), 0, st, P, in, out, u);
+hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, hipStream_t st) {
+  switch (tn.fd_rows) {
+    case 1: hipLaunchKernelGGL(k_fd<1>, dim3(xcd_grid(fd_tiles<1>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
+    case 2: hipLaunchKernelGGL(k_fd<2>, dim3(xcd_grid(fd_tiles<2>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
+    default: hipLaunchKernelGGL(k_fd<4>, dim3(xcd_grid(fd_tiles<4>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
+  }
+  return hipGetLastError();
+}
+
+int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
+  if (collide) return tn.collide_rows == 1 ? collide_tiles<1>(P.nx, P.ny) : collide_tiles<2>(P.nx, P.ny);
+  return tn.fd_rows == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_rows == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
+}
+
+hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur, bool pop16,
+                                Tuning tn, hipStream_t st) {
+  const dim3 grid(xcd_grid(tiles));
+  if (tn.collide_rows == 1) {
+    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 1>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+    else hipLaunchKernelGGL((k_collide_batch<float, 1>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+  } else {
+    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 2>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+    else hipLaunchKernelGGL((k_collide_batch<float, 2>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src, Tuning tn,
+                           hipStream_t st) {
+  const dim3 grid(xcd_grid(tiles)), blk(FD_TX, FD_TY);
+  switch (tn.fd_rows) {
+    case 1: hipLaunchKernelGGL(k_fd_batch<1>, grid, blk, 0, st, mem, first, count, tiles, src); break;
+    case 2: hipLaunchKernelGGL(k_fd_batch<2>, grid, blk, 0, st, mem, first, count, tiles, src); break;
+    default: hipLaunchKernelGGL(k_fd_batch<4>, grid, blk, 0, st, mem, first, count, tiles, src); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
-  const dim3 grid(xcd_grid(collide_tiles(P)));
-  if (P.pop16)
-    hipLaunchKernelGGL((k_collide<true, _Float16>), grid, dim3(CT_THREADS), 0, st, P, in, nullptr, aux);
-  else
-    hipLaunchKernelGGL((k_collide<true, float>), grid, dim3(CT_THREADS), 0, st, P, in, nullptr, aux);
+  const dim3 grid(xcd_grid(collide_tiles<2>(P.nx, P.ny)));
+  TFAN_POP_DISPATCH((k_collide<true, float, 2>), (k_collide<true, _Float16, 2>), grid, dim3(CT_THREADS), 0, st, P,
+                    in, nullptr, aux);
   return hipGetLastError();
 }
 

@@ -94,3 +94,22 @@ def random_velocity(nx: int, ny: int, seed: int, amp: float = 1e-3) -> np.ndarra
     """A seeded smooth-free random velocity plane pair [2, ny, nx] (ux, uy)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-amp, amp, size=(2, ny, nx))
+
+
+def sweep_members(count: int = 64, seed: int = 5) -> list:
+    """The batched parameter sweep: `count` members with square sizes drawn from
+    {128, 256, 512} and zeta in [0, 0.02], lam in [0.3, 1.0], K in [0.01, 0.1],
+    mean composition in [-0.4, 0.4] (uniform, seeded); per-member initial-condition
+    seed 5000 + i.  Returns a list of dicts: params, phi_mean, seed."""
+    rng = np.random.default_rng(seed)
+    sizes = rng.choice([128, 256, 512], size=count)
+    zeta = rng.uniform(0.0, 0.02, size=count)
+    lam = rng.uniform(0.3, 1.0, size=count)
+    K = rng.uniform(0.01, 0.1, size=count)
+    phibar = rng.uniform(-0.4, 0.4, size=count)
+    out = []
+    for i in range(count):
+        n = int(sizes[i])
+        out.append(dict(params=base_params(n, n, zeta=float(zeta[i]), lam=float(lam[i]), K=float(K[i])),
+                        phi_mean=float(phibar[i]), seed=5000 + i))
+    return out

@@ -26,7 +26,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 ALG_BYTES = {
     "step": 168,        # whole coupled step: 2*9*4*2 + 3*4*2
     "collide": 172,     # pull+write populations (144), read phi/Q (12), write u_a, u_c (16)
-    "substep": 40,      # read phi/Q (12) and u_a/u_c (16), write phi/Q (12)
+    "substep": 40,      # one sub-step: read phi/Q (12) and u_a/u_c (16), write phi/Q (12)
+    "substeps": 40,     # all n_sub sub-steps in one launch: the same 40 B, once per step
 }
 
 
@@ -118,7 +119,7 @@ def bench_sweep(args):
            "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"sweep_64: {len(members)} members, sizes 128/256/512, {sites} sites",
-                      "tuning": {"collide_rows": tuning[0], "fd_rows": tuning[1]},
+                      "tuning": {"collide_rows": tuning[0], "fd_shape": tuning[1]},
                       "autotune_ms_per_step": round(tuned_ms, 4)},
            "sequential_value": round(sites * args.steps / wall_seq / 1e6, 1),
            "batch_speedup": round(wall_seq / wall, 3)}
@@ -135,6 +136,8 @@ def main():
                     help="population storage (f16: binary16 deviations, float32 arithmetic)")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", default="", metavar="C,F",
+                    help="launch shape collide_rows,fd_shape (default: the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -170,6 +173,9 @@ def main():
     nx, ny = p["nx"], p["ny"]
     ic = initial_fields(nx, ny, seed=w["seeds"][0], phi_mean=w["phi_mean"])
     sim = Sim(p, device="cuda:0")
+    if args.tuning:
+        sim.set_tuning(*[int(v) for v in args.tuning.split(",")])
+    tuning = sim.get_tuning()
     sim.init_fields(**ic)
     print(f"[bench] {args.workload}: {nx}x{ny}, warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
@@ -223,7 +229,8 @@ def main():
         "config": {"workload": f"{args.workload}: {nx}x{ny} periodic, "
                                f"{'plain float32' if p['storage'] == 0 else 'binary16-storage'} path, "
                                f"zeta={p['zeta']}, n_sub={p['n_sub']}, seed {w['seeds'][0]}",
-                   "nx": nx, "ny": ny, "n_sub": p["n_sub"], "parallelism": "single GPU"},
+                   "nx": nx, "ny": ny, "n_sub": p["n_sub"], "parallelism": "single GPU",
+                   "tuning": {"collide_rows": tuning[0], "fd_shape": tuning[1]}},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2)},

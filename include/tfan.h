@@ -158,11 +158,15 @@ int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n);
 int tfan_kernel_count(void);
 const char* tfan_kernel_name(int id);
 
-/* Launch shape of the two hot kernels: collide_rows in {1, 2} rows of sites per
- * thread of the collision kernel, fd_rows in {1, 2, 4} of the sub-step kernel.
- * Results are bitwise identical for every shape; only the speed differs. */
-int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_rows);
-int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_rows);
+/* Launch shape of the hot kernels: collide_rows in {1, 2} rows of sites per
+ * thread of the collision kernel; fd_shape in {1, 2, 4}: one launch per
+ * finite-difference sub-step with that many rows per thread, or in {16, 32}: all
+ * n_sub sub-steps of a step in one launch on 64 x fd_shape tiles (temporal
+ * blocking; used when n_sub <= 5, otherwise the 4-row per-sub-step launch runs).
+ * Default (2, 16).  Results are bitwise identical for every shape; only the speed
+ * differs.  Other values: TFAN_EINVAL. */
+int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape);
+int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_shape);
 
 /* Autotuner: runs `steps` steps (after one warm-up step) with every launch
  * shape, keeps the fastest, restores the state it started from (checkpoint
@@ -198,8 +202,8 @@ int tfan_batch_step(tfan_batch* b, int64_t n);                           /* asyn
 int tfan_batch_get_fields(tfan_batch* b, int32_t member, double* phi, double* qxx, double* qxy,
                           double* u_a, double* u_p, double* rho_a, double* rho_p);
 int tfan_batch_diagnostics(tfan_batch* b, int32_t member, tfan_diag* out);
-int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_rows);
-int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_rows);
+int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_shape);
+int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_shape);
 int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step);
 int tfan_batch_sync(tfan_batch* b);
 void tfan_batch_destroy(tfan_batch* b);

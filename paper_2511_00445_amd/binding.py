@@ -226,8 +226,10 @@ class Sim:
     def kernel_timing(self, cap: int):
         self._check(self.lib.tfan_kernel_timing(self._handle, int(cap)))
 
-    def set_tuning(self, collide_rows: int, fd_rows: int):
-        self._check(self.lib.tfan_set_tuning(self._handle, int(collide_rows), int(fd_rows)))
+    def set_tuning(self, collide_rows: int, fd_shape: int):
+        """collide_rows in {1, 2}; fd_shape in {1, 2, 4} (one launch per sub-step) or
+        {16, 32} (all sub-steps of a step in one launch, n_sub <= 5)."""
+        self._check(self.lib.tfan_set_tuning(self._handle, int(collide_rows), int(fd_shape)))
 
     def get_tuning(self) -> tuple:
         c, f = ctypes.c_int32(), ctypes.c_int32()
@@ -325,8 +327,8 @@ class Batch:
         out["status"] = rc
         return out
 
-    def set_tuning(self, collide_rows: int, fd_rows: int):
-        self._check(self.lib.tfan_batch_set_tuning(self._handle, int(collide_rows), int(fd_rows)))
+    def set_tuning(self, collide_rows: int, fd_shape: int):
+        self._check(self.lib.tfan_batch_set_tuning(self._handle, int(collide_rows), int(fd_shape)))
 
     def get_tuning(self) -> tuple:
         c, f = ctypes.c_int32(), ctypes.c_int32()

@@ -192,6 +192,25 @@ int download(tfan_sim* s, double* dst, const float* src, size_t count, std::vect
 
 }  // namespace
 
+static bool valid_shape(int32_t collide_rows, int32_t fd_shape) {
+  return (collide_rows == 1 || collide_rows == 2) &&
+         (fd_shape == 1 || fd_shape == 2 || fd_shape == 4 || fd_shape == 16 || fd_shape == 32);
+}
+static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16 or 32";
+// Shapes the autotuners try: every collide_rows with every fd_shape (the fused
+// shapes only where n_sub allows them).
+static std::vector<tfan::Tuning> tuning_candidates(int n_sub) {
+  std::vector<tfan::Tuning> out;
+  for (int c : {1, 2})
+    for (int f : {1, 2, 4, 16, 32}) {
+      tfan::Tuning t;
+      t.collide_rows = c;
+      t.fd_shape = f;
+      if (f < 16 || tfan::fd_fused(t, n_sub)) out.push_back(t);
+    }
+  return out;
+}
+
 extern "C" {
 
 int tfan_check_params(const tfan_params* p) {
@@ -277,11 +296,18 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
     }
     // sub-steps alternate the phi/Q buffers; the collision above already read state a
     int src = a;
-    for (int m = 0; m < s->dp.n_sub; ++m) {
-      TimedLaunch t(s, tfan::K_FD);
-      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, s->stream);
+    if (tfan::fd_fused(s->tune, s->dp.n_sub)) {
+      TimedLaunch t(s, tfan::K_FDN);
+      hipError_t e = tfan::launch_fd(s->dp, state_of(s, a), state_of(s, b), s->U, s->tune, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
-      src = 1 - src;
+      src = b;
+    } else {
+      for (int m = 0; m < s->dp.n_sub; ++m) {
+        TimedLaunch t(s, tfan::K_FD);
+        hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, s->stream);
+        if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
+        src = 1 - src;
+      }
     }
     // keep the new populations and fields under one index
     if (src != b) {
@@ -449,19 +475,18 @@ int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n) {
   return TFAN_OK;
 }
 
-int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_rows) {
+int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
-  if ((collide_rows != 1 && collide_rows != 2) || (fd_rows != 1 && fd_rows != 2 && fd_rows != 4))
-    return fail(s, TFAN_EINVAL, "collide_rows must be 1 or 2 and fd_rows 1, 2 or 4");
+  if (!valid_shape(collide_rows, fd_shape)) return fail(s, TFAN_EINVAL, kShapeMsg);
   s->tune.collide_rows = collide_rows;
-  s->tune.fd_rows = fd_rows;
+  s->tune.fd_shape = fd_shape;
   return TFAN_OK;
 }
 
-int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_rows) {
-  if (!s || !collide_rows || !fd_rows) return fail(nullptr, TFAN_EINVAL, "NULL argument");
+int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_shape) {
+  if (!s || !collide_rows || !fd_shape) return fail(nullptr, TFAN_EINVAL, "NULL argument");
   *collide_rows = s->tune.collide_rows;
-  *fd_rows = s->tune.fd_rows;
+  *fd_shape = s->tune.fd_shape;
   return TFAN_OK;
 }
 
@@ -475,13 +500,10 @@ int tfan_autotune(tfan_sim* s, int32_t steps, double* best_ms_per_step) {
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return hip_fail(s, e, "autotune events");
-  const int crows[2] = {1, 2}, frows[3] = {1, 2, 4};
   tfan::Tuning best = s->tune;
   float best_ms = -1.f;
-  for (int c : crows)
-    for (int f : frows) {
-      s->tune.collide_rows = c;
-      s->tune.fd_rows = f;
+  for (const tfan::Tuning& cand : tuning_candidates(s->dp.n_sub)) {
+      s->tune = cand;
       if ((rc = tfan_step(s, 1))) break;  // warm-up
       (void)hipEventRecord(e0, s->stream);
       if ((rc = tfan_step(s, steps))) break;
@@ -507,7 +529,7 @@ int tfan_autotune(tfan_sim* s, int32_t steps, double* best_ms_per_step) {
 int tfan_kernel_count(void) { return tfan::K_COUNT; }
 
 const char* tfan_kernel_name(int id) {
-  static const char* names[tfan::K_COUNT] = {"collide", "substep", "init", "fields", "diagnostics"};
+  static const char* names[tfan::K_COUNT] = {"collide", "substep", "init", "fields", "diagnostics", "substeps"};
   return (id >= 0 && id < tfan::K_COUNT) ? names[id] : "";
 }
 
@@ -685,8 +707,9 @@ int tfan_batch_step(tfan_batch* b, int64_t nsteps) {
                                               b->stream);
     if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch collide launch: ") + hipGetErrorString(e));
     int src = b->cur;
-    for (int m = 0; m < b->n_sub; ++m) {
-      e = tfan::launch_fd_batch(b->table, b->first_f, count, b->tiles_f, src, b->tune, b->stream);
+    const int launches = tfan::fd_fused(b->tune, b->n_sub) ? 1 : b->n_sub;
+    for (int m = 0; m < launches; ++m) {
+      e = tfan::launch_fd_batch(b->table, b->first_f, count, b->tiles_f, src, b->tune, b->n_sub, b->stream);
       if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch sub-step launch: ") + hipGetErrorString(e));
       src = 1 - src;
     }
@@ -726,19 +749,18 @@ int tfan_batch_diagnostics(tfan_batch* b, int32_t member, tfan_diag* out) {
   return rc;
 }
 
-int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_rows) {
+int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_shape) {
   if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
-  if ((collide_rows != 1 && collide_rows != 2) || (fd_rows != 1 && fd_rows != 2 && fd_rows != 4))
-    return bfail(b, TFAN_EINVAL, "collide_rows must be 1 or 2 and fd_rows 1, 2 or 4");
+  if (!valid_shape(collide_rows, fd_shape)) return bfail(b, TFAN_EINVAL, kShapeMsg);
   b->tune.collide_rows = collide_rows;
-  b->tune.fd_rows = fd_rows;
+  b->tune.fd_shape = fd_shape;
   return upload_first(b);
 }
 
-int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_rows) {
-  if (!b || !collide_rows || !fd_rows) return bfail(nullptr, TFAN_EINVAL, "NULL argument");
+int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_shape) {
+  if (!b || !collide_rows || !fd_shape) return bfail(nullptr, TFAN_EINVAL, "NULL argument");
   *collide_rows = b->tune.collide_rows;
-  *fd_rows = b->tune.fd_rows;
+  *fd_shape = b->tune.fd_shape;
   return TFAN_OK;
 }
 
@@ -756,13 +778,11 @@ int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step) 
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return bfail(b, TFAN_EHIP, "autotune events");
-  const int crows[2] = {1, 2}, frows[3] = {1, 2, 4};
   tfan::Tuning best = b->tune;
   float best_ms = -1.f;
   int rc = TFAN_OK;
-  for (int c : crows)
-    for (int f : frows) {
-      if ((rc = tfan_batch_set_tuning(b, c, f))) break;
+  for (const tfan::Tuning& cand : tuning_candidates(b->n_sub)) {
+      if ((rc = tfan_batch_set_tuning(b, cand.collide_rows, cand.fd_shape))) break;
       if ((rc = tfan_batch_step(b, 1))) break;
       (void)hipEventRecord(e0, b->stream);
       if ((rc = tfan_batch_step(b, steps))) break;
@@ -784,7 +804,7 @@ int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step) 
   }
   b->cur = 0;
   b->step = step0;
-  const int r3 = tfan_batch_set_tuning(b, best.collide_rows, best.fd_rows);
+  const int r3 = tfan_batch_set_tuning(b, best.collide_rows, best.fd_shape);
   if (rc) return rc;
   if (r3) return r3;
   if (best_ms_per_step) *best_ms_per_step = best_ms / steps;

@@ -40,12 +40,17 @@ struct DevState {
   float* q;        // [2][n] (Qxx, Qxy)
 };
 
-// Launch shape of the two hot kernels (results do not depend on it):
-// collide_rows in {1, 2} rows of sites per thread, fd_rows in {1, 2, 4}.
+// Launch shape of the hot kernels (results do not depend on it):
+// collide_rows in {1, 2} rows of sites per thread; fd_shape in {1, 2, 4}: one
+// launch per sub-step with that many rows per thread, or {16, 32}: all sub-steps
+// of a step in one launch on 64 x fd_shape tiles (n_sub <= kFusedMaxSub; larger
+// n_sub falls back to one launch per sub-step with 4 rows per thread).
+constexpr int kFusedMaxSub = 5;
 struct Tuning {
   int collide_rows = 2;
-  int fd_rows = 4;
+  int fd_shape = 16;
 };
+inline bool fd_fused(const Tuning& tn, int n_sub) { return tn.fd_shape >= 16 && n_sub <= kFusedMaxSub; }
 
 // One member of a batch of independent simulations (device-resident table).
 struct BatchMember {
@@ -55,14 +60,14 @@ struct BatchMember {
 };
 
 // Kernel ids for timing.
-enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_COUNT };
+enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_FDN, K_COUNT };
 
 // Launchers (return hipGetLastError() after the launch).
 hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
                        hipStream_t st);
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
                           Tuning tn, hipStream_t st);
-// One finite-difference sub-step.
+// One finite-difference sub-step, or all n_sub of them when fd_fused(tn, n_sub).
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
                      Tuning tn, hipStream_t st);
 // Tiles of one member for the collision (collide = true) or sub-step kernel.
@@ -70,8 +75,9 @@ int batch_tiles(const DevParams& P, Tuning tn, bool collide);
 // Batched launches over the tiles of all members; first[m] = first tile of member m.
 hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur,
                                 bool pop16, Tuning tn, hipStream_t st);
+// (all members share n_sub)
 hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src,
-                           Tuning tn, hipStream_t st);
+                           Tuning tn, int n_sub, hipStream_t st);
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: drho_a, drho_p, u_a, u_p*/,
                          hipStream_t st);
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,

@@ -414,6 +414,220 @@ __global__ void __launch_bounds__(FD_TX * FD_TY) k_fd_batch(const BatchMember* _
   fd_tile<R>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m]);
 }
 
+// ---------------------------------------------------------------------------
+// All n_sub <= 5 sub-steps of a step in one launch (temporal blocking in LDS).
+// The Cahn-Hilliard and Beris-Edwards sub-steps do not depend on each other, so
+// the two fields grow their halos separately: phi needs phi at distance 2 per
+// sub-step (through mu), Q needs Q at distance 1.  A block stages, for a 64 x TH
+// tile, phi and u_c with a halo of 10 and Q and u_a with a halo of 5, then runs
+// the sub-steps on boxes that shrink by 2 (phi) and 1 (Q) per sub-step, and
+// writes only the final phi and Q of its tile.  The arithmetic of each site
+// update is that of fd_tile, term for term, so both paths give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int FF_X = 64, FF_MAXSUB = 5;
+constexpr int FF_HA = 2 * FF_MAXSUB;  // halo of the phi / mu / u_c frame
+constexpr int FF_HB = FF_MAXSUB;      // halo of the Q / u_a frame
+template <int TH> struct Fused {
+  static constexpr int AW = FF_X + 2 * FF_HA, AH = TH + 2 * FF_HA;
+  static constexpr int BW = FF_X + 2 * FF_HB, BH = TH + 2 * FF_HB;
+  static constexpr int NT = TH >= 32 ? 1024 : 512;
+  static constexpr int KA = (AW * AH + NT - 1) / NT, KB = (BW * BH + NT - 1) / NT;
+  // largest boxes updated into registers: phi with halo 2 n_sub - 2, Q with n_sub - 1
+  static constexpr int KP = ((FF_X + 4 * FF_MAXSUB - 4) * (TH + 4 * FF_MAXSUB - 4) + NT - 1) / NT;
+  static constexpr int KQ = ((FF_X + 2 * FF_MAXSUB - 2) * (TH + 2 * FF_MAXSUB - 2) + NT - 1) / NT;
+};
+template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
+  return ((nx + FF_X - 1) / FF_X) * ((ny + TH - 1) / TH);
+}
+
+// Row and column of entry c of a box w entries wide (c < 2^13, w >= 64): the
+// rounded product is at least 0.5 / w away from an integer, far above its error.
+__device__ __forceinline__ int box_row(int c, float inv_w) { return (int)(((float)c + 0.5f) * inv_w); }
+
+template <int TH>
+__device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState& in, const DevState& out,
+                                              const float* __restrict__ U, int tile) {
+  using F = Fused<TH>;
+  constexpr int AW = F::AW, AH = F::AH, BW = F::BW, BH = F::BH, NT = F::NT;
+  __shared__ float sphi[AH * AW], smu[AH * AW], sucx[AH * AW], sucy[AH * AW];
+  __shared__ float sqx[BH * BW], sqy[BH * BW], suax[BH * BW], suay[BH * BW];
+  __shared__ unsigned scol[AW], srow[AH];
+  const int nx = P.nx, ny = P.ny, n = P.n, S = P.n_sub;
+  const int gx = (nx + FF_X - 1) / FF_X;
+  const int x0 = (tile % gx) * FF_X, y0 = (tile / gx) * TH;
+  const int tid = threadIdx.x;
+  // periodic source column / row offset of every frame entry (small grids wrap
+  // more than once)
+  for (int i = tid; i < AW + AH; i += NT) {
+    if (i < AW) {
+      const int g = (x0 - FF_HA + i) % nx;
+      scol[i] = (unsigned)(g < 0 ? g + nx : g);
+    } else {
+      const int g = (y0 - FF_HA + (i - AW)) % ny;
+      srow[i - AW] = (unsigned)(g < 0 ? g + ny : g) * (unsigned)nx;
+    }
+  }
+  __syncthreads();
+  // stage the frames; every load is issued before the first LDS store
+  {
+    const Plane ph = plane(in.phi, n), qx = plane(in.q, n), qy = plane(in.q + n, n);
+    const Plane uax = plane(U, n), uay = plane(U + n, n), ucx = plane(U + 2 * n, n), ucy = plane(U + 3 * n, n);
+    float va[F::KA][3], vb[F::KB][4];
+#pragma unroll
+    for (int k = 0; k < F::KA; ++k) {
+      const int c = min(tid + k * NT, AW * AH - 1);
+      const int cy = c / AW, cx = c - cy * AW;
+      const unsigned g = srow[cy] + scol[cx];
+      va[k][0] = ldg(ph, g);
+      va[k][1] = ldg(ucx, g);
+      va[k][2] = ldg(ucy, g);
+    }
+#pragma unroll
+    for (int k = 0; k < F::KB; ++k) {
+      const int c = min(tid + k * NT, BW * BH - 1);
+      const int cy = c / BW, cx = c - cy * BW;
+      const unsigned g = srow[cy + FF_HA - FF_HB] + scol[cx + FF_HA - FF_HB];
+      vb[k][0] = ldg(qx, g);
+      vb[k][1] = ldg(qy, g);
+      vb[k][2] = ldg(uax, g);
+      vb[k][3] = ldg(uay, g);
+    }
+#pragma unroll
+    for (int k = 0; k < F::KA; ++k) {
+      const int c = tid + k * NT;
+      if (c < AW * AH) {
+        sphi[c] = va[k][0];
+        sucx[c] = va[k][1];
+        sucy[c] = va[k][2];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < F::KB; ++k) {
+      const int c = tid + k * NT;
+      if (c < BW * BH) {
+        sqx[c] = vb[k][0];
+        sqy[c] = vb[k][1];
+        suax[c] = vb[k][2];
+        suay[c] = vb[k][3];
+      }
+    }
+  }
+  __syncthreads();
+  const Plane ophi = plane(out.phi, n), oqx = plane(out.q, n), oqy = plane(out.q + n, n);
+  float pn[F::KP], qn[F::KQ][2];
+  for (int m = 1; m <= S; ++m) {
+    const int r = 2 * (S - m), s = S - m;  // halos of the boxes updated in this sub-step
+    // (1) mu on the phi box of halo r + 1
+    {
+      const int w = FF_X + 2 * (r + 1), cnt = w * (TH + 2 * (r + 1)), off = FF_HA - (r + 1);
+      const float inv = 1.f / (float)w;
+      for (int c = tid; c < cnt; c += NT) {
+        const int cy = box_row(c, inv), cx = c - cy * w;
+        const int p = (cy + off) * AW + (cx + off);
+        smu[p] = chem_pot(sphi[p], sphi[p + 1], sphi[p - 1], sphi[p + AW], sphi[p - AW], P);
+      }
+    }
+    // (2) Beris-Edwards update on the Q box of halo s, into registers
+    const int wq = FF_X + 2 * s, cq = wq * (TH + 2 * s), oq = FF_HB - s;
+    const float invq = 1.f / (float)wq;
+#pragma unroll
+    for (int k = 0; k < F::KQ; ++k) {
+      const int c = tid + k * NT;
+      if (c < cq) {
+        const int cy = box_row(c, invq), cx = c - cy * wq;
+        const int p = (cy + oq) * BW + (cx + oq);
+        const float2 ue = make_float2(suax[p + 1], suay[p + 1]), uw = make_float2(suax[p - 1], suay[p - 1]);
+        const float2 un = make_float2(suax[p + BW], suay[p + BW]), us = make_float2(suax[p - BW], suay[p - BW]);
+        const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (un.x - us.x);
+        const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (un.y - us.y);
+        const float2 nq = be_update(make_float2(sqx[p], sqy[p]), make_float2(sqx[p + 1], sqy[p + 1]),
+                                    make_float2(sqx[p - 1], sqy[p - 1]), make_float2(sqx[p + BW], sqy[p + BW]),
+                                    make_float2(sqx[p - BW], sqy[p - BW]), make_float2(suax[p], suay[p]),
+                                    wxx, wxy, wyx, wyy, P.h, P);
+        qn[k][0] = nq.x;
+        qn[k][1] = nq.y;
+      }
+    }
+    __syncthreads();
+    // (3) Cahn-Hilliard update on the phi box of halo r, into registers
+    const int wp = FF_X + 2 * r, cp = wp * (TH + 2 * r), op = FF_HA - r;
+    const float invp = 1.f / (float)wp;
+#pragma unroll
+    for (int k = 0; k < F::KP; ++k) {
+      const int c = tid + k * NT;
+      if (c < cp) {
+        const int cy = box_row(c, invp), cx = c - cy * wp;
+        const int p = (cy + op) * AW + (cx + op);
+        const float div = 0.5f * (sphi[p + 1] * sucx[p + 1] - sphi[p - 1] * sucx[p - 1]) +
+                          0.5f * (sphi[p + AW] * sucy[p + AW] - sphi[p - AW] * sucy[p - AW]);
+        const float lapmu = (smu[p + 1] + smu[p - 1]) + (smu[p + AW] + smu[p - AW]) - 4.f * smu[p];
+        pn[k] = sphi[p] + P.h * (P.M * lapmu - div);
+      }
+    }
+    __syncthreads();
+    // (4) write back: into the frames, or the tile to the output after the last sub-step
+    if (m < S) {
+#pragma unroll
+      for (int k = 0; k < F::KP; ++k) {
+        const int c = tid + k * NT;
+        if (c < cp) {
+          const int cy = box_row(c, invp), cx = c - cy * wp;
+          sphi[(cy + op) * AW + (cx + op)] = pn[k];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < F::KQ; ++k) {
+        const int c = tid + k * NT;
+        if (c < cq) {
+          const int cy = box_row(c, invq), cx = c - cy * wq;
+          const int p = (cy + oq) * BW + (cx + oq);
+          sqx[p] = qn[k][0];
+          sqy[p] = qn[k][1];
+        }
+      }
+      __syncthreads();
+    } else {
+      // r = s = 0: both boxes are the tile, entry c = cy * 64 + cx
+#pragma unroll
+      for (int k = 0; k < F::KQ; ++k) {
+        const int c = tid + k * NT;
+        const int cy = c / FF_X, cx = c - cy * FF_X;
+        if (c < FF_X * TH && x0 + cx < nx && y0 + cy < ny) {
+          const unsigned o = (unsigned)(y0 + cy) * (unsigned)nx + (unsigned)(x0 + cx);
+          stg(oqx, o, qn[k][0]);
+          stg(oqy, o, qn[k][1]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < F::KP; ++k) {
+        const int c = tid + k * NT;
+        const int cy = c / FF_X, cx = c - cy * FF_X;
+        if (c < FF_X * TH && x0 + cx < nx && y0 + cy < ny)
+          stg(ophi, (unsigned)(y0 + cy) * (unsigned)nx + (unsigned)(x0 + cx), pn[k]);
+      }
+    }
+  }
+}
+
+template <int TH>
+__global__ void __launch_bounds__(Fused<TH>::NT) k_fd_fused(DevParams P, DevState in, DevState out,
+                                                             const float* __restrict__ U) {
+  const int tile = xcd_tile(fused_tiles<TH>(P.nx, P.ny));
+  if (tile < 0) return;
+  fd_fused_tile<TH>(P, in, out, U, tile);
+}
+
+template <int TH>
+__global__ void __launch_bounds__(Fused<TH>::NT) k_fd_fused_batch(const BatchMember* __restrict__ mem,
+                                                                   const int* __restrict__ first, int count,
+                                                                   int tiles, int src) {
+  const int tile = xcd_tile(tiles);
+  if (tile < 0) return;
+  const int m = batch_member(first, count, tile);
+  const DevParams P = mem[m].P;
+  fd_fused_tile<TH>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m]);
+}
+
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
 // stored f*_i(x) = f^eq_i(u(x + c_i)) - w_i rho0.
 template <typename PT>
@@ -590,7 +804,16 @@ hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u
 }
 
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, hipStream_t st) {
-  switch (tn.fd_rows) {
+  if (fd_fused(tn, P.n_sub)) {
+    if (tn.fd_shape == 16)
+      hipLaunchKernelGGL(k_fd_fused<16>, dim3(xcd_grid(fused_tiles<16>(P.nx, P.ny))), dim3(Fused<16>::NT), 0, st,
+                         P, in, out, u);
+    else
+      hipLaunchKernelGGL(k_fd_fused<32>, dim3(xcd_grid(fused_tiles<32>(P.nx, P.ny))), dim3(Fused<32>::NT), 0, st,
+                         P, in, out, u);
+    return hipGetLastError();
+  }
+  switch (tn.fd_shape) {
     case 1: hipLaunchKernelGGL(k_fd<1>, dim3(xcd_grid(fd_tiles<1>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
     case 2: hipLaunchKernelGGL(k_fd<2>, dim3(xcd_grid(fd_tiles<2>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
     default: hipLaunchKernelGGL(k_fd<4>, dim3(xcd_grid(fd_tiles<4>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
@@ -600,7 +823,8 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
 
 int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
   if (collide) return tn.collide_rows == 1 ? collide_tiles<1>(P.nx, P.ny) : collide_tiles<2>(P.nx, P.ny);
-  return tn.fd_rows == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_rows == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
+  if (fd_fused(tn, P.n_sub)) return tn.fd_shape == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
+  return tn.fd_shape == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_shape == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
 }
 
 hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur, bool pop16,
@@ -617,9 +841,16 @@ hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int co
 }
 
 hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src, Tuning tn,
-                           hipStream_t st) {
+                           int n_sub, hipStream_t st) {
   const dim3 grid(xcd_grid(tiles)), blk(FD_TX, FD_TY);
-  switch (tn.fd_rows) {
+  if (fd_fused(tn, n_sub)) {
+    if (tn.fd_shape == 16)
+      hipLaunchKernelGGL(k_fd_fused_batch<16>, grid, dim3(Fused<16>::NT), 0, st, mem, first, count, tiles, src);
+    else
+      hipLaunchKernelGGL(k_fd_fused_batch<32>, grid, dim3(Fused<32>::NT), 0, st, mem, first, count, tiles, src);
+    return hipGetLastError();
+  }
+  switch (tn.fd_shape) {
     case 1: hipLaunchKernelGGL(k_fd_batch<1>, grid, blk, 0, st, mem, first, count, tiles, src); break;
     case 2: hipLaunchKernelGGL(k_fd_batch<2>, grid, blk, 0, st, mem, first, count, tiles, src); break;
     default: hipLaunchKernelGGL(k_fd_batch<4>, grid, blk, 0, st, mem, first, count, tiles, src); break;

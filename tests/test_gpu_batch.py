@@ -8,7 +8,8 @@ from oracle.coracle import COracle
 from paper_2511_00445_amd.workloads import base_params, initial_fields
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(c, f) for c in (1, 2) for f in (1, 2, 4)]
+# fd_shape 1, 2, 4: one launch per sub-step; 16, 32: all sub-steps in one launch
+SHAPES = [(c, f) for c in (1, 2) for f in (1, 2, 4, 16, 32)]
 
 
 def say(msg):
@@ -37,6 +38,20 @@ def test_results_independent_of_launch_shape(gpu, storage):
         assert np.array_equal(single(p, ic, 15, shape).get_state(), ref), shape
 
 
+@pytest.mark.parametrize("n_sub,nx,ny", [(1, 8, 8), (2, 13, 70), (3, 130, 9), (4, 64, 64), (5, 8, 33),
+                                         (6, 40, 24), (8, 24, 40)])
+def test_fused_substeps_match_per_substep_launches(gpu, n_sub, nx, ny):
+    """All sub-steps in one launch (temporal blocking) against one launch per
+    sub-step: bitwise equal for every n_sub, on grids smaller than a tile and with
+    ragged edges (n_sub > 5 runs the per-sub-step path under either setting)."""
+    say(f"case: fused sub-steps n_sub {n_sub}, {nx}x{ny}")
+    p = base_params(nx, ny, zeta=0.03, lam=1.2, n_sub=n_sub)
+    ic = initial_fields(nx, ny, seed=30 + n_sub, phi_noise=0.5, S0=0.3)
+    ref = single(p, ic, 12, (2, 4)).get_state()
+    for f in (16, 32):
+        assert np.array_equal(single(p, ic, 12, (2, f)).get_state(), ref), f
+
+
 def test_autotune_keeps_state(gpu):
     from paper_2511_00445_amd import Sim
     say("case: autotune")
@@ -57,7 +72,7 @@ def _members():
             dict(p=base_params(128, 128, tau_a=0.8, tau_p=1.3), ic=initial_fields(128, 128, seed=4, phi_mean=-0.3))]
 
 
-@pytest.mark.parametrize("shape", [(2, 4), (1, 1)])
+@pytest.mark.parametrize("shape", [(2, 4), (1, 1), (2, 32), (1, 16)])
 def test_batch_members_match_single_runs(gpu, shape):
     from paper_2511_00445_amd import Batch
     say(f"case: batch vs single, shape {shape}")

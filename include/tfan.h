@@ -142,6 +142,18 @@ size_t tfan_state_bytes(const tfan_sim* s);
 int tfan_get_state(tfan_sim* s, void* host, size_t bytes);
 int tfan_set_state(tfan_sim* s, const void* host, size_t bytes);
 
+/* Device-side state exchange (for the convolutional surrogate, tfan_cnn.h).
+ * tfan_export_state writes phi, Qxx, Qxy, u_a (x, y) and u_p (x, y) of the
+ * current state as float32 planes [7][ny][nx] into dev_out (caller-owned device
+ * memory); the velocities are the ones tfan_get_fields returns.
+ * tfan_import_state sets phi and Q from dev_in [7][ny][nx] and both population
+ * sets to f^eq(rho0, u) of its velocities (density deviations restart at zero,
+ * as after tfan_init_fields), and sets the step counter to `step` (>= 0).
+ * Both are enqueued on the solver's stream and do not synchronise; the
+ * device arrays must stay valid until the stream reaches them. */
+int tfan_export_state(tfan_sim* s, float* dev_out);
+int tfan_import_state(tfan_sim* s, const float* dev_in, int64_t step);
+
 /* Wait for the handle's stream; reports execution errors. */
 int tfan_sync(tfan_sim* s);
 

@@ -7,9 +7,10 @@ The surrogate of the Numerical Simulation / Results workflow advances the solver
 state (phi, Qxx, Qxy, u_a, u_p: 7 channels) by k lattice steps.  Its network:
 six 3x3 convolutions on the periodic grid, 7 -> 48 -> 48 -> 48 -> 48 -> 48 -> 7
 channels, SiLU (x sigmoid(x)) after the first five, acting on the state divided
-by fixed per-channel scales s; the last layer's output y is the scaled increment,
-prediction = x + s * y.  Loss: mean over samples, channels and sites of
-(y - (x_target - x) / s)^2.  Optimiser: Adam (Kingma and Ba, 2015).
+by fixed per-channel input scales s_in; the last layer's output y is the
+increment in units of per-channel output scales s_out, prediction = x + s_out y.
+Loss: mean over samples, channels and sites of (y - (x_target - x) / s_out)^2.
+Optimiser: Adam (Kingma and Ba, 2015).
 
 Quantisation points (quantise=True) follow the stated precision of the GPU
 path: the network input, the weights, every stored activation and every
@@ -155,11 +156,12 @@ def adam(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def predict(layers, x, scales, quantise=True):
+def predict(layers, x, s_in, s_out, quantise=True):
     """State after k steps from state x [B][7][H][W] (physical units)."""
-    s = np.asarray(scales, dtype=np.float64)[None, :, None, None]
-    y, _ = forward(layers, x / s, quantise)
-    return x + s * y
+    si = np.asarray(s_in, dtype=np.float64)[None, :, None, None]
+    so = np.asarray(s_out, dtype=np.float64)[None, :, None, None]
+    y, _ = forward(layers, x / si, quantise)
+    return x + so * y
 
 
 def init_params(seed=0, gain=1.0, zero_last=True):

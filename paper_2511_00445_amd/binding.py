@@ -94,6 +94,25 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_batch_destroy": (None, [_vp]),
         "tfan_batch_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
+        "tfan_export_state": (ctypes.c_int, [_vp, _vp]),
+        "tfan_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int64]),
+        "tfan_cnn_param_count": (ctypes.c_int64, []),
+        "tfan_cnn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                       ctypes.c_int32]),
+        "tfan_cnn_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp,
+                                           ctypes.c_size_t, _vp, _P(_vp)]),
+        "tfan_cnn_set_params": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
+        "tfan_cnn_get_params": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
+        "tfan_cnn_set_scales": (ctypes.c_int, [_vp, _P(ctypes.c_float), _P(ctypes.c_float)]),
+        "tfan_cnn_forward": (ctypes.c_int, [_vp, _vp, _vp]),
+        "tfan_cnn_gradients": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _P(ctypes.c_int32),
+                                              _P(ctypes.c_float), _dp]),
+        "tfan_cnn_train_step": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int64, _P(ctypes.c_int32), ctypes.c_float,
+                                               _dp]),
+        "tfan_cnn_compare": (ctypes.c_int, [_vp, _vp, _vp, _dp]),
+        "tfan_cnn_sync": (ctypes.c_int, [_vp]),
+        "tfan_cnn_destroy": (None, [_vp]),
+        "tfan_cnn_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_destroy": (None, [_vp]),
         "tfan_last_error": (ctypes.c_char_p, [_vp]),
     }
@@ -129,6 +148,15 @@ def workspace_bytes(p: dict) -> int:
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _check_dev(t, shape=None):
+    """A contiguous float32 tensor on a HIP device (optionally of a given trailing shape)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TfanError(TFAN_EINVAL, "expected a contiguous float32 device tensor")
+    if shape is not None and tuple(t.shape[-len(shape):]) != tuple(shape):
+        raise TfanError(TFAN_EINVAL, f"expected trailing shape {shape}, got {tuple(t.shape)}")
 
 
 def _f64(a, shape):
@@ -219,6 +247,16 @@ class Sim:
 
     def sync(self):
         self._check(self.lib.tfan_sync(self._handle))
+
+    def export_state(self, out):
+        """Write (phi, Qxx, Qxy, u_a, u_p) as float32 [7][ny][nx] into the device tensor out."""
+        _check_dev(out, (7, self.ny, self.nx))
+        self._check(self.lib.tfan_export_state(self._handle, _vp(out.data_ptr())))
+
+    def import_state(self, x, step: int):
+        """Set phi, Q and equilibrium populations from the device tensor x [7][ny][nx]."""
+        _check_dev(x, (7, self.ny, self.nx))
+        self._check(self.lib.tfan_import_state(self._handle, _vp(x.data_ptr()), int(step)))
 
     def step_count(self) -> int:
         return int(self.lib.tfan_step_count(self._handle))
@@ -347,6 +385,113 @@ class Batch:
         if getattr(self, "_handle", None) and self._handle.value:
             self.lib.tfan_batch_destroy(self._handle)
             self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cnn:
+    """The convolutional surrogate network (include/tfan_cnn.h) on one stream.
+
+    batch samples of ny x nx sites per call; train reserves the backward-pass
+    buffers.  States are float32 device tensors [B][7][ny][nx]."""
+
+    def __init__(self, batch: int, ny: int, nx: int, train: bool = False, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the network runs only on the GPU")
+        self.lib = load_library()
+        self.batch, self.ny, self.nx, self.train = int(batch), int(ny), int(nx), bool(train)
+        nbytes = int(self.lib.tfan_cnn_workspace_bytes(self.batch, self.ny, self.nx, int(self.train)))
+        if nbytes == 0:
+            raise TfanError(TFAN_EINVAL, "batch >= 1 and ny, nx positive multiples of 16 required")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self._handle = _vp()
+        rc = self.lib.tfan_cnn_create(self.batch, self.ny, self.nx, int(self.train), _vp(aligned), nbytes,
+                                      _vp(self.stream.cuda_stream), ctypes.byref(self._handle))
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_cnn_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_cnn_last_error(self._handle).decode())
+
+    @staticmethod
+    def param_count() -> int:
+        return int(load_library().tfan_cnn_param_count())
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32).ravel()
+        if th.size != self.param_count():
+            raise TfanError(TFAN_EINVAL, f"expected {self.param_count()} parameters")
+        self._check(self.lib.tfan_cnn_set_params(self._handle, th.ctypes.data_as(_P(ctypes.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        th = np.empty(self.param_count(), dtype=np.float32)
+        self._check(self.lib.tfan_cnn_get_params(self._handle, th.ctypes.data_as(_P(ctypes.c_float))))
+        return th
+
+    def set_scales(self, s_in, s_out):
+        a = np.ascontiguousarray(s_in, dtype=np.float32).ravel()
+        b = np.ascontiguousarray(s_out, dtype=np.float32).ravel()
+        if a.size != 7 or b.size != 7:
+            raise TfanError(TFAN_EINVAL, "7 input and 7 output scales required")
+        self._check(self.lib.tfan_cnn_set_scales(self._handle, a.ctypes.data_as(_P(ctypes.c_float)),
+                                                 b.ctypes.data_as(_P(ctypes.c_float))))
+
+    def forward(self, x, out):
+        _check_dev(x, (self.batch, 7, self.ny, self.nx))
+        _check_dev(out, (self.batch, 7, self.ny, self.nx))
+        self._check(self.lib.tfan_cnn_forward(self._handle, _vp(x.data_ptr()), _vp(out.data_ptr())))
+
+    def _batch(self, X, T, idx):
+        _check_dev(X, (7, self.ny, self.nx))
+        _check_dev(T, (7, self.ny, self.nx))
+        if X.shape != T.shape or X.dim() != 4:
+            raise TfanError(TFAN_EINVAL, "X and T must be stacks [n][7][ny][nx] of equal size")
+        ix = np.ascontiguousarray(idx, dtype=np.int32).ravel()
+        if ix.size != self.batch:
+            raise TfanError(TFAN_EINVAL, f"{self.batch} sample indices required")
+        return ix
+
+    def gradients(self, X, T, idx):
+        """(loss, gradient vector) of the batch X[idx] -> T[idx]."""
+        ix = self._batch(X, T, idx)
+        g = np.empty(self.param_count(), dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(self.lib.tfan_cnn_gradients(self._handle, _vp(X.data_ptr()), _vp(T.data_ptr()), X.shape[0],
+                                                ix.ctypes.data_as(_P(ctypes.c_int32)),
+                                                g.ctypes.data_as(_P(ctypes.c_float)), ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, X, T, idx, lr: float, want_loss: bool = True):
+        ix = self._batch(X, T, idx)
+        loss = ctypes.c_double()
+        self._check(self.lib.tfan_cnn_train_step(self._handle, _vp(X.data_ptr()), _vp(T.data_ptr()), X.shape[0],
+                                                 ix.ctypes.data_as(_P(ctypes.c_int32)), float(lr),
+                                                 ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def compare(self, a, b) -> np.ndarray:
+        """[7][2]: per channel sum (a - b)^2 and sum b^2."""
+        _check_dev(a, (self.batch, 7, self.ny, self.nx))
+        _check_dev(b, (self.batch, 7, self.ny, self.nx))
+        out = np.empty(14)
+        self._check(self.lib.tfan_cnn_compare(self._handle, _vp(a.data_ptr()), _vp(b.data_ptr()), _ptr(out)))
+        return out.reshape(7, 2)
+
+    def sync(self):
+        self._check(self.lib.tfan_cnn_sync(self._handle))
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            self.lib.tfan_cnn_destroy(self._handle)
+            self._handle = None
 
     def __del__(self):
         try:

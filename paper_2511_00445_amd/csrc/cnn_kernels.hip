@@ -1,0 +1,484 @@
+// gfx950 kernels of the convolutional surrogate: periodic 3x3 convolutions as
+// implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x16_bf16, fp32
+// accumulation), their weight gradients, the loss, Adam and data packing.
+//
+// Activations are stored channels-last (NHWC) in bfloat16 so that one k-block of
+// 16 channels of a site is contiguous; pre-activations kept for the backward pass
+// are fp32.  MFMA operand layout (16x16x16): lane l holds A[l%16][4(l/16)+v],
+// B[4(l/16)+v][l%16] and D[4(l/16)+v][l%16], v = 0..3.
+#include "cnn_internal.h"
+
+namespace tcnn {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Round to nearest even (NaN kept quiet).
+__device__ __forceinline__ bf16 to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ---------------------------------------------------------------------------
+// Convolution.  A block computes a 16 x 16 tile of sites for all CO output
+// channels: M = 256 sites (wave w owns rows 4w..4w+3, one 16-site M-tile each),
+// N = CO, K = 9 taps x CI channels, 16 channels of one tap per MFMA.  The input
+// tile with a halo of 1 and the layer's weights are staged in LDS; the pixel
+// and weight strides carry 4 extra bf16 so the 8-byte fragment reads of 16
+// lanes fall in distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int kHalo = kTile + 2;
+
+template <int CI, int CO, int MODE>
+__global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                              const float* __restrict__ bias, const float* __restrict__ z_below,
+                                              bf16* __restrict__ out_bf, float* __restrict__ out_f, int H, int W) {
+  constexpr int PS = CI + 4, WS = 9 * CI + 4, NT = CO / 16, KC = CI / 16;
+  __shared__ __attribute__((aligned(16))) bf16 patch[kHalo * kHalo * PS];
+  __shared__ __attribute__((aligned(16))) bf16 wts[CO * WS];
+  const int tiles_x = W / kTile, tiles_y = H / kTile;
+  const int b = blockIdx.x / (tiles_x * tiles_y), t = blockIdx.x % (tiles_x * tiles_y);
+  const int y0 = (t / tiles_x) * kTile, x0 = (t % tiles_x) * kTile;
+  const int tid = threadIdx.x;
+  // stage the input tile (periodic halo) and the weights, 4 channels per load
+  constexpr int GP = CI / 4;
+  for (int i = tid; i < kHalo * kHalo * GP; i += 256) {
+    const int pix = i / GP, g = i - pix * GP;
+    const int py = pix / kHalo, px = pix - py * kHalo;
+    const int gy = wrap(y0 + py - 1, H), gx = wrap(x0 + px - 1, W);
+    const uint2 v = *reinterpret_cast<const uint2*>(in + (((size_t)b * H + gy) * W + gx) * CI + 4 * g);
+    *reinterpret_cast<uint2*>(&patch[pix * PS + 4 * g]) = v;
+  }
+  constexpr int GW = 9 * CI / 4;
+  for (int i = tid; i < CO * GW; i += 256) {
+    const int o = i / GW, g = i - o * GW;
+    *reinterpret_cast<uint2*>(&wts[o * WS + 4 * g]) = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3, dx = tap - 3 * dy;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      bf16x4 a[4], bw[NT];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = 4 * wave + m;  // tile row of this M-tile; site x = li
+        a[m] = *reinterpret_cast<const bf16x4*>(&patch[((r + dy) * kHalo + li + dx) * PS + kc * 16 + 4 * lg]);
+      }
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+        bw[n] = *reinterpret_cast<const bf16x4*>(&wts[(n * 16 + li) * WS + tap * CI + kc * 16 + 4 * lg]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bw[n], acc[m][n], 0, 0, 0);
+    }
+  }
+  // epilogue: D[4 lg + v][li] -> site x = 4 lg + v of tile row r, channel n * 16 + li
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int y = y0 + 4 * wave + m;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int c = n * 16 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const size_t o = (((size_t)b * H + y) * W + x0 + 4 * lg + v) * CO + c;
+        const float s = acc[m][n][v];
+        if (MODE == kSilu) {
+          const float z = s + bias[c];
+          if (out_f) out_f[o] = z;
+          out_bf[o] = to_bf16(z * sigmoid(z));
+        } else if (MODE == kLinear) {
+          out_f[o] = s + bias[c];
+        } else {
+          const float z = z_below[o];
+          const float sg = sigmoid(z);
+          out_bf[o] = to_bf16(s * (sg * (1.f + z * (1.f - sg))));
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient gW[co][tap][ci] = sum over sites p of g[p][co] a[p + off(tap)][ci]:
+// a GEMM with M = CO, N = 9 CI and K = sites.  A block walks a range of 16 x 16
+// tiles; per tile g is staged transposed ([co][site]) and the input tile with
+// its halo channel-major ([ci][y][x]), and each MFMA takes the 16 sites of one
+// tile row as its k-block.  The 9 * CI / 16 N-tiles are dealt round-robin to the
+// 4 waves.  Bias gradient: row sums of the staged g.
+// ---------------------------------------------------------------------------
+constexpr int kDwBlocks = 256;
+constexpr int GS = kTile * kTile + 4;  // site stride of the transposed gradient tile
+constexpr int AS = kHalo + 2;          // row stride of the channel-major input tile
+
+template <int CI, int CO>
+__global__ void __launch_bounds__(256) k_weight_grad(const bf16* __restrict__ g, const bf16* __restrict__ a,
+                                                     float* __restrict__ partial, float* __restrict__ partial_b,
+                                                     int B, int H, int W) {
+  constexpr int MT = CO / 16, NTT = 9 * CI / 16, NW = (NTT + 3) / 4;
+  __shared__ __attribute__((aligned(16))) bf16 gT[CO * GS];
+  __shared__ __attribute__((aligned(16))) bf16 aT[CI * kHalo * AS];
+  __shared__ float bsum[4][CO];
+  const int tiles_x = W / kTile, tiles_y = H / kTile, tiles = B * tiles_x * tiles_y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
+  f32x4 acc[MT][NW];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;  // thread (co = tid % CO, part = tid / CO) sums sites part*64 .. +63
+  const int bco = tid % CO, bpart = tid / CO;
+  for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int b = t / (tiles_x * tiles_y), r = t % (tiles_x * tiles_y);
+    const int y0 = (r / tiles_x) * kTile, x0 = (r % tiles_x) * kTile;
+    __syncthreads();  // previous tile's reads are done
+    for (int i = tid; i < kTile * kTile * CO; i += 256) {
+      const int s = i / CO, c = i - s * CO;
+      gT[c * GS + s] = g[(((size_t)b * H + y0 + s / kTile) * W + x0 + s % kTile) * CO + c];
+    }
+    for (int i = tid; i < kHalo * kHalo * CI; i += 256) {
+      const int pix = i / CI, c = i - pix * CI;
+      const int py = pix / kHalo, px = pix - py * kHalo;
+      aT[(c * kHalo + py) * AS + px] = a[(((size_t)b * H + wrap(y0 + py - 1, H)) * W + wrap(x0 + px - 1, W)) * CI + c];
+    }
+    __syncthreads();
+    if (bpart < 4) {
+      for (int s = bpart * 64; s < bpart * 64 + 64; ++s) bacc += from_bf16(gT[bco * GS + s]);
+    }
+#pragma unroll 1
+    for (int row = 0; row < kTile; ++row) {
+      bf16x4 af[MT];
+#pragma unroll
+      for (int m = 0; m < MT; ++m)  // A[i][k]: co = m * 16 + li, site = (row, 4 lg + v)
+        af[m] = *reinterpret_cast<const bf16x4*>(&gT[(m * 16 + li) * GS + row * kTile + 4 * lg]);
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        const int nt = wave + 4 * j;
+        if (nt < NTT) {
+          const int tap = nt / (CI / 16), kc = nt - tap * (CI / 16);
+          const int dy = tap / 3, dx = tap - 3 * dy;
+          // B[k][j]: site (row, 4 lg + v) shifted by the tap, channel kc * 16 + li
+          const bf16* src = &aT[((kc * 16 + li) * kHalo + row + dy) * AS + 4 * lg + dx];
+          bf16x4 bf;
+          bf[0] = (short)src[0];
+          bf[1] = (short)src[1];
+          bf[2] = (short)src[2];
+          bf[3] = (short)src[3];
+#pragma unroll
+          for (int m = 0; m < MT; ++m)
+            acc[m][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[m], bf, acc[m][j], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D[4 lg + v][li]: co = m * 16 + 4 lg + v, column (tap, kc * 16 + li)
+  float* out = partial + (size_t)blockIdx.x * CO * 9 * CI;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const int nt = wave + 4 * j;
+    if (nt < NTT) {
+      const int tap = nt / (CI / 16), kc = nt - tap * (CI / 16);
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[((m * 16 + 4 * lg + v) * 9 + tap) * CI + kc * 16 + li] = acc[m][j][v];
+    }
+  }
+  if (bpart < 4) bsum[bpart][bco] = bacc;
+  __syncthreads();
+  if (tid < CO) partial_b[(size_t)blockIdx.x * CO + tid] = (bsum[0][tid] + bsum[1][tid]) + (bsum[2][tid] + bsum[3][tid]);
+}
+
+// Sum of the block partials in block order into the natural layout of the real channels.
+__global__ void k_weight_grad_reduce(const float* __restrict__ partial, const float* __restrict__ partial_b,
+                                     int nblk, int ci, int co, int ci_real, int co_real, float* __restrict__ gW,
+                                     float* __restrict__ gb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nW = co_real * ci_real * 9;
+  if (i < nW) {
+    const int o = i / (ci_real * 9), rem = i - o * ci_real * 9, c = rem / 9, tap = rem - c * 9;
+    const size_t col = ((size_t)o * 9 + tap) * ci + c, stride = (size_t)co * 9 * ci;
+    float s = 0.f;
+    for (int k = 0; k < nblk; ++k) s += partial[k * stride + col];
+    gW[i] = s;
+  } else if (i < nW + co_real) {
+    const int o = i - nW;
+    float s = 0.f;
+    for (int k = 0; k < nblk; ++k) s += partial_b[(size_t)k * co + o];
+    gb[o] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packing, loss, prediction, Adam, weight layouts, comparison.
+// ---------------------------------------------------------------------------
+__global__ void k_pack(const float* __restrict__ x, int64_t stride, const int* __restrict__ idx,
+                       const float* __restrict__ inv_scale, bf16* __restrict__ a0, int B, int H, int W) {
+  const int64_t hw = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B * hw) return;
+  const int b = (int)(p / hw);
+  const int64_t s = p - b * hw;
+  const float* xs = x + (int64_t)idx[b] * stride;
+  bf16 v[kPadIO];
+#pragma unroll
+  for (int c = 0; c < kPadIO; ++c) v[c] = c < kChannels ? to_bf16(xs[c * hw + s] * inv_scale[c]) : (bf16)0;
+  uint4* dst = reinterpret_cast<uint4*>(a0 + p * kPadIO);
+  dst[0] = make_uint4(v[0] | (unsigned)v[1] << 16, v[2] | (unsigned)v[3] << 16, v[4] | (unsigned)v[5] << 16,
+                      v[6] | (unsigned)v[7] << 16);
+  dst[1] = make_uint4(v[8] | (unsigned)v[9] << 16, v[10] | (unsigned)v[11] << 16, v[12] | (unsigned)v[13] << 16,
+                      v[14] | (unsigned)v[15] << 16);
+}
+
+constexpr int kLossThreads = 256;
+__global__ void __launch_bounds__(kLossThreads) k_loss(const float* __restrict__ y, const float* __restrict__ x,
+                                                       const float* __restrict__ target, int64_t stride,
+                                                       const int* __restrict__ idx, const float* __restrict__ inv_scale,
+                                                       bf16* __restrict__ g, double* __restrict__ partial, int B, int H,
+                                                       int W) {
+  const int64_t hw = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float scale_g = (float)(2.0 / ((double)B * hw * kChannels));
+  double acc = 0.0;
+  if (p < B * hw) {
+    const int b = (int)(p / hw);
+    const int64_t s = p - b * hw;
+    const float* xs = x + (int64_t)idx[b] * stride;
+    const float* ts = target + (int64_t)idx[b] * stride;
+    bf16 v[kPadIO];
+#pragma unroll
+    for (int c = 0; c < kPadIO; ++c) {
+      if (c < kChannels) {
+        const float d = y[p * kPadIO + c] - (ts[c * hw + s] - xs[c * hw + s]) * inv_scale[c];
+        acc += (double)d * (double)d;
+        v[c] = to_bf16(scale_g * d);
+      } else {
+        v[c] = 0;
+      }
+    }
+    uint4* dst = reinterpret_cast<uint4*>(g + p * kPadIO);
+    dst[0] = make_uint4(v[0] | (unsigned)v[1] << 16, v[2] | (unsigned)v[3] << 16, v[4] | (unsigned)v[5] << 16,
+                        v[6] | (unsigned)v[7] << 16);
+    dst[1] = make_uint4(v[8] | (unsigned)v[9] << 16, v[10] | (unsigned)v[11] << 16, v[12] | (unsigned)v[13] << 16,
+                        v[14] | (unsigned)v[15] << 16);
+  }
+  // block sum in a fixed order
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  __shared__ double red[kLossThreads / 64];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void k_sum_partials(const double* __restrict__ partial, int n, double scale, double* __restrict__ out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) acc += partial[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (threadIdx.x == 0) *out = acc * scale;
+}
+
+__global__ void k_unpack(const float* __restrict__ y, const float* __restrict__ x, const float* __restrict__ scale,
+                         float* __restrict__ out, int B, int H, int W) {
+  const int64_t hw = (int64_t)H * W;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= B * hw) return;
+  const int b = (int)(p / hw);
+  const int64_t s = p - b * hw;
+#pragma unroll
+  for (int c = 0; c < kChannels; ++c) {
+    const int64_t o = ((int64_t)b * kChannels + c) * hw + s;
+    out[o] = x[o] + scale[c] * y[p * kPadIO + c];
+  }
+}
+
+// omb1 = 1 - beta1 and omb2 = 1 - beta2 come rounded from their exact values
+// (1 - 0.999f is 0.00099998713 in fp32, not 0.001).
+__global__ void k_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float omb1, float b2, float omb2,
+                       float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = grad[i];
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+__global__ void k_pack_weights(const float* __restrict__ Wt, const float* __restrict__ bt, int ci_real, int co_real,
+                               int ci, int co, bf16* __restrict__ wf, bf16* __restrict__ wb, float* __restrict__ bias) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over co * 9 * ci
+  if (i < co) bias[i] = i < co_real ? bt[i] : 0.f;
+  if (i >= co * 9 * ci) return;
+  const int o = i / (9 * ci), rem = i - o * 9 * ci, tap = rem / ci, c = rem - tap * ci;
+  const float val = (o < co_real && c < ci_real) ? Wt[((size_t)o * ci_real + c) * 9 + tap] : 0.f;
+  const bf16 h = to_bf16(val);
+  wf[i] = h;
+  wb[((size_t)c * 9 + (8 - tap)) * co + o] = h;
+}
+
+constexpr int kCmpThreads = 256;
+__global__ void __launch_bounds__(kCmpThreads) k_compare(const float* __restrict__ a, const float* __restrict__ b,
+                                                         int64_t plane, int B, double* __restrict__ partial) {
+  // partial[block][14]: per channel sum (a - b)^2, sum b^2
+  double s[2 * kChannels];
+#pragma unroll
+  for (int k = 0; k < 2 * kChannels; ++k) s[k] = 0.0;
+  const int64_t total = (int64_t)B * plane;
+  for (int64_t p = (int64_t)blockIdx.x * kCmpThreads + threadIdx.x; p < total; p += (int64_t)gridDim.x * kCmpThreads) {
+    const int bb = (int)(p / plane);
+    const int64_t q = p - bb * plane;
+#pragma unroll
+    for (int c = 0; c < kChannels; ++c) {
+      const int64_t o = ((int64_t)bb * kChannels + c) * plane + q;
+      const double d = (double)a[o] - (double)b[o], r = (double)b[o];
+      s[2 * c] += d * d;
+      s[2 * c + 1] += r * r;
+    }
+  }
+  __shared__ double red[kCmpThreads / 64][2 * kChannels];
+#pragma unroll
+  for (int k = 0; k < 2 * kChannels; ++k) {
+    double v = s[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kChannels)
+    partial[(size_t)blockIdx.x * 2 * kChannels + threadIdx.x] =
+        (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void k_compare_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= 2 * kChannels) return;
+  double s = 0.0;
+  for (int i = 0; i < nblk; ++i) s += partial[(size_t)i * 2 * kChannels + k];
+  out[k] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_conv(int ci, int co, ConvMode mode, const bf16* in, const bf16* w, const float* bias,
+                       const float* z_below, bf16* out_bf, float* out_f, int B, int H, int W, hipStream_t st) {
+  const dim3 grid((unsigned)(B * (H / kTile) * (W / kTile))), blk(256);
+#define TCNN_CONV(CI_, CO_, M_) \
+  hipLaunchKernelGGL((k_conv<CI_, CO_, M_>), grid, blk, 0, st, in, w, bias, z_below, out_bf, out_f, H, W)
+  if (ci == kPadIO && co == kHidden && mode == kSilu) TCNN_CONV(kPadIO, kHidden, kSilu);
+  else if (ci == kHidden && co == kHidden && mode == kSilu) TCNN_CONV(kHidden, kHidden, kSilu);
+  else if (ci == kHidden && co == kPadIO && mode == kLinear) TCNN_CONV(kHidden, kPadIO, kLinear);
+  else if (ci == kHidden && co == kHidden && mode == kBackward) TCNN_CONV(kHidden, kHidden, kBackward);
+  else if (ci == kPadIO && co == kHidden && mode == kBackward) TCNN_CONV(kPadIO, kHidden, kBackward);
+  else return hipErrorInvalidValue;
+#undef TCNN_CONV
+  return hipGetLastError();
+}
+
+int dw_blocks(int B, int H, int W) {
+  const int tiles = B * (H / kTile) * (W / kTile);
+  return tiles < kDwBlocks ? tiles : kDwBlocks;
+}
+
+hipError_t launch_weight_grad(int ci, int co, int ci_real, int co_real, const bf16* g, const bf16* a,
+                              float* partial, float* partial_b, float* gW, float* gb, int B, int H, int W,
+                              hipStream_t st) {
+  const int nblk = dw_blocks(B, H, W);
+  if (ci == kPadIO && co == kHidden)
+    hipLaunchKernelGGL((k_weight_grad<kPadIO, kHidden>), dim3(nblk), dim3(256), 0, st, g, a, partial, partial_b, B, H, W);
+  else if (ci == kHidden && co == kHidden)
+    hipLaunchKernelGGL((k_weight_grad<kHidden, kHidden>), dim3(nblk), dim3(256), 0, st, g, a, partial, partial_b, B, H, W);
+  else if (ci == kHidden && co == kPadIO)
+    hipLaunchKernelGGL((k_weight_grad<kHidden, kPadIO>), dim3(nblk), dim3(256), 0, st, g, a, partial, partial_b, B, H, W);
+  else
+    return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = co_real * ci_real * 9 + co_real;
+  hipLaunchKernelGGL(k_weight_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partial, partial_b, nblk, ci, co,
+                     ci_real, co_real, gW, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* x, int64_t sample_stride, const int* idx, const float* inv_scale, bf16* a0,
+                       int B, int H, int W, hipStream_t st) {
+  const int64_t n = (int64_t)B * H * W;
+  hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, sample_stride, idx, inv_scale, a0,
+                     B, H, W);
+  return hipGetLastError();
+}
+
+int loss_blocks(int B, int H, int W) { return (int)(((int64_t)B * H * W + kLossThreads - 1) / kLossThreads); }
+
+hipError_t launch_loss(const float* y, const float* x, const float* target, int64_t sample_stride, const int* idx,
+                       const float* inv_scale, bf16* g, double* partial, double* loss, int B, int H, int W,
+                       hipStream_t st) {
+  const int nblk = loss_blocks(B, H, W);
+  hipLaunchKernelGGL(k_loss, dim3(nblk), dim3(kLossThreads), 0, st, y, x, target, sample_stride, idx, inv_scale, g,
+                     partial, B, H, W);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, partial, nblk, 1.0 / ((double)B * H * W * kChannels),
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const float* y, const float* x, const float* scale, float* out, int B, int H, int W,
+                         hipStream_t st) {
+  const int64_t n = (int64_t)B * H * W;
+  hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, x, scale, out, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int64_t n, float lr, double beta1,
+                       double beta2, float eps, float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, grad, m, v, n, lr,
+                     (float)beta1, (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float* W, const float* b, int ci_real, int co_real, int ci, int co, bf16* wf,
+                               bf16* wb, float* bias, hipStream_t st) {
+  const int n = co * 9 * ci;
+  hipLaunchKernelGGL(k_pack_weights, dim3((n + 255) / 256), dim3(256), 0, st, W, b, ci_real, co_real, ci, co, wf, wb,
+                     bias);
+  return hipGetLastError();
+}
+
+int compare_blocks(int64_t plane, int B) {
+  const int64_t n = (plane * B + kCmpThreads - 1) / kCmpThreads;
+  return (int)(n < 1024 ? n : 1024);
+}
+
+hipError_t launch_compare(const float* a, const float* b, int64_t plane, int B, double* partial, double* out,
+                          hipStream_t st) {
+  const int nblk = compare_blocks(plane, B);
+  hipLaunchKernelGGL(k_compare, dim3(nblk), dim3(kCmpThreads), 0, st, a, b, plane, B, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_compare_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+}  // namespace tcnn

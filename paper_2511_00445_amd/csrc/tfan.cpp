@@ -439,6 +439,41 @@ int tfan_sync(tfan_sim* s) {
 
 int64_t tfan_step_count(const tfan_sim* s) { return s ? s->step : -1; }
 
+int tfan_export_state(tfan_sim* s, float* out) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!out) return fail(s, TFAN_EINVAL, "output array is NULL");
+  const size_t n = (size_t)s->dp.n;
+  {
+    TimedLaunch t(s, tfan::K_FIELDS);
+    hipError_t e = tfan::launch_fields(s->dp, state_of(s, s->cur), s->aux, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "fields kernel launch");
+  }
+  // aux holds [drho_a, drho_p, u_a (2), u_p (2)]
+  hipError_t e = hipMemcpyAsync(out, s->phi[s->cur], n * 4, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out + n, s->q[s->cur], 2 * n * 4, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out + 3 * n, s->aux + 2 * n, 4 * n * 4, hipMemcpyDeviceToDevice, s->stream);
+  return e == hipSuccess ? TFAN_OK : hip_fail(s, e, "state export");
+}
+
+int tfan_import_state(tfan_sim* s, const float* in, int64_t step) {
+  if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!in) return fail(s, TFAN_EINVAL, "input array is NULL");
+  if (step < 0) return fail(s, TFAN_EINVAL, "step must be >= 0");
+  const size_t n = (size_t)s->dp.n;
+  s->cur = 0;
+  hipError_t e = hipMemcpyAsync(s->phi[0], in, n * 4, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->q[0], in + n, 2 * n * 4, hipMemcpyDeviceToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(s->aux, in + 3 * n, 4 * n * 4, hipMemcpyDeviceToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "state import");
+  {
+    TimedLaunch t(s, tfan::K_INIT);
+    e = tfan::launch_init(s->dp, s->aux, state_of(s, 0), s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "init kernel launch");
+  }
+  s->step = step;
+  return TFAN_OK;
+}
+
 int tfan_kernel_timing(tfan_sim* s, int64_t cap) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (cap < 0 || cap > (int64_t(1) << 20)) return fail(s, TFAN_EINVAL, "cap must be in [0, 2^20]");

@@ -1,5 +1,5 @@
 """CPU checks of the C ABI: the library loads, exports every function that
-include/tfan.h declares, and validates parameters on the host (no GPU call)."""
+include/*.h declares, and validates parameters on the host (no GPU call)."""
 import ctypes
 import os
 import re
@@ -10,19 +10,22 @@ import paper_2511_00445_amd as T
 from paper_2511_00445_amd.binding import tfan_params, tfan_diag, make_params
 from paper_2511_00445_amd.workloads import workload_params
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tfan.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+HEADER = os.path.join(INCLUDE, "tfan.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(path=HEADER):
+    text = open(path).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tfan_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tfan_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function():
     lib = T.load_library()
-    names = declared_functions()
-    assert len(names) >= 18
+    headers = sorted(f for f in os.listdir(INCLUDE) if f.endswith(".h"))
+    assert "tfan.h" in headers and "tfan_cnn.h" in headers
+    names = [n for h in headers for n in declared_functions(os.path.join(INCLUDE, h))]
+    assert len(names) >= 30
     for name in names:
         assert hasattr(lib, name), name
 
@@ -61,3 +64,16 @@ def test_create_rejects_without_touching_the_gpu():
     assert lib.tfan_create(ctypes.byref(p), ctypes.c_void_p(100), 1 << 30, None, ctypes.byref(h)) == T.TFAN_EINVAL
     assert lib.tfan_step(None, 1) == T.TFAN_EINVAL
     assert lib.tfan_kernel_count() >= 2
+
+
+def test_cnn_host_validation():
+    lib = T.load_library()
+    assert T.Cnn.param_count() == 89239
+    assert lib.tfan_cnn_workspace_bytes(1, 64, 64, 0) > 0
+    assert lib.tfan_cnn_workspace_bytes(2, 64, 64, 1) > lib.tfan_cnn_workspace_bytes(2, 64, 64, 0)
+    for bad in ((0, 64, 64), (1, 63, 64), (1, 64, 8), (1, 0, 64)):
+        assert lib.tfan_cnn_workspace_bytes(*bad, 1) == 0
+    h = ctypes.c_void_p()
+    assert lib.tfan_cnn_create(1, 64, 64, 0, None, 0, None, ctypes.byref(h)) == T.TFAN_EINVAL
+    assert lib.tfan_cnn_create(1, 64, 64, 0, ctypes.c_void_p(256), 10, None, ctypes.byref(h)) == T.TFAN_ENOMEM
+    assert b"workspace too small" in lib.tfan_cnn_last_error(None)

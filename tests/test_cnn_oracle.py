@@ -120,7 +120,7 @@ def test_untrained_network_is_identity_and_equivariant():
     rng = np.random.default_rng(8)
     layers = C.init_params(seed=9)
     x = rng.normal(size=(1, 7, 8, 8))
-    np.testing.assert_array_equal(C.predict(layers, x, np.ones(7)), x)
+    np.testing.assert_array_equal(C.predict(layers, x, np.ones(7), np.full(7, 0.5)), x)
     layers = C.init_params(seed=9, zero_last=False)
     y, _ = C.forward(layers, x)
     ys, _ = C.forward(layers, np.roll(x, (2, -3), axis=(2, 3)))

@@ -1,0 +1,169 @@
+"""The surrogate network's HIP kernels (through the C ABI) against the FP64 oracle
+oracle/cnn_oracle.py, which applies the same bfloat16 quantisation points.
+
+Tolerances.  Every stored activation and back-propagated gradient is a bfloat16
+rounding of an fp32 value that differs from the oracle's fp64 value by about
+1e-5 relative (fp32 sums of up to 432 products); the rounding then lands on a
+different bfloat16 neighbour for a small fraction of elements (~1e-3), each off
+by one bfloat16 unit (2^-8 relative).  Over six layers this gives a relative L2
+difference of a few 1e-4; the bounds below are 2e-3 (network output) and 5e-3
+(weight and bias gradients).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cnn_oracle as C
+from paper_2511_00445_amd.workloads import base_params, initial_fields
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
+
+
+def setup(seed, nsamp, H, W, zero_last=False):
+    rng = np.random.default_rng(seed)
+    layers = C.init_params(seed=seed, zero_last=zero_last)
+    theta = C.flatten(layers).astype(np.float32)
+    layers = C.unflatten(theta.astype(np.float64))  # the oracle sees the fp32 parameters
+    s_in = rng.uniform(0.5, 2.0, size=7).astype(np.float32)
+    s_out = rng.uniform(0.05, 0.2, size=7).astype(np.float32)
+    X = (rng.normal(size=(nsamp, 7, H, W)) * s_in[None, :, None, None]).astype(np.float32)
+    T = (X + rng.normal(size=X.shape) * s_out[None, :, None, None]).astype(np.float32)
+    return layers, theta, (s_in, s_out), X, T
+
+
+def inv(s):
+    """The reciprocal the library forms (fp32), as float64 broadcastable over [B][7][H][W]."""
+    return (1.0 / s.astype(np.float32)).astype(np.float64)[None, :, None, None]
+
+
+def test_forward_matches_oracle(gpu):
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn forward B=2 32x48")
+    layers, theta, scales, X, _ = setup(1, 2, 32, 48)
+    net = Cnn(2, 32, 48)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    x = torch.from_numpy(X).cuda()
+    out = torch.empty_like(x)
+    net.forward(x, out)
+    net.sync()
+    got = out.cpu().numpy().astype(np.float64)
+    so = scales[1].astype(np.float64)[None, :, None, None]
+    y_gpu = (got - X) / so
+    y_ref, _ = C.forward(layers, X.astype(np.float64) * inv(scales[0]))
+    e = rel(y_gpu, y_ref)
+    say(f"forward: relative L2 of the network output {e:.2e}")
+    assert e <= 2e-3
+    ref = C.predict(layers, X.astype(np.float64), scales[0].astype(np.float64), scales[1].astype(np.float64))
+    assert rel(got - X, ref - X) <= 2e-3
+
+
+def test_gradients_match_oracle(gpu):
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn gradients B=2 32x48")
+    layers, theta, scales, X, T = setup(2, 3, 32, 48)
+    net = Cnn(2, 32, 48, train=True)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    idx = [2, 0]
+    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), idx)
+    xn = X[idx].astype(np.float64) * inv(scales[0])
+    tn = (T[idx].astype(np.float32) - X[idx].astype(np.float32)).astype(np.float64) * inv(scales[1])
+    lref, gref = C.loss_and_grads(layers, xn, tn)
+    say(f"loss gpu {loss:.8e} oracle {lref:.8e}")
+    assert abs(loss - lref) <= 1e-4 * lref
+    gg = C.unflatten(g.astype(np.float64))
+    for li in range(C.LAYERS):
+        ew, eb = rel(gg[li][0], gref[li][0]), rel(gg[li][1], gref[li][1])
+        say(f"layer {li + 1}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        assert ew <= 5e-3 and eb <= 5e-3, (li, ew, eb)
+
+
+def test_adam_step_closed_form(gpu):
+    """First Adam step: bias-corrected moments are g and g^2, so each parameter
+    moves by lr g / (|g| + eps) with g the batch gradient."""
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn adam step")
+    _, theta, scales, X, T = setup(3, 2, 16, 32)
+    net = Cnn(2, 16, 32, train=True)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    _, g = net.gradients(Xd, Td, [0, 1])
+    lr = 1e-3
+    net.train_step(Xd, Td, [0, 1], lr)
+    th1 = net.get_params().astype(np.float64)
+    g = g.astype(np.float64)
+    want = theta.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(th1 - want) - 1e-6 * lr - 2e-7 * np.abs(want)) <= 0.0
+
+
+def test_training_reduces_the_loss(gpu):
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn fits one batch")
+    _, theta, scales, X, T = setup(4, 2, 32, 32, zero_last=True)
+    net = Cnn(2, 32, 32, train=True)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    losses = [net.train_step(Xd, Td, [0, 1], 2e-3) for _ in range(60)]
+    say(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.6 * losses[0]
+
+
+def test_state_exchange_with_the_solver(gpu):
+    """export -> import reproduces what init_fields does with the same values."""
+    import torch
+    from paper_2511_00445_amd import Sim
+    say("case: solver state export/import 48x32")
+    p = base_params(48, 32, zeta=0.02)
+    a = Sim(p)
+    a.init_fields(**initial_fields(48, 32, seed=5, phi_noise=0.3, S0=0.2))
+    a.step(25)
+    x = torch.empty((7, 32, 48), dtype=torch.float32, device="cuda")
+    a.export_state(x)
+    a.sync()
+    f = a.get_fields()
+    xh = x.cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(xh[0], f["phi"])
+    np.testing.assert_array_equal(xh[1], f["qxx"])
+    np.testing.assert_array_equal(xh[3:5], f["u_a"])
+    np.testing.assert_array_equal(xh[5:7], f["u_p"])
+    b, c = Sim(p), Sim(p)
+    b.import_state(x, 25)
+    c.init_fields(phi=xh[0], qxx=xh[1], qxy=xh[2], u_a=xh[3:5], u_p=xh[5:7])
+    assert b.step_count() == 25
+    sb, sc = b.get_state(), c.get_state()
+    np.testing.assert_array_equal(sb[8:], sc[8:])  # all but the step counter
+
+
+def test_cnn_argument_errors(gpu):
+    import torch
+    import paper_2511_00445_amd as T
+    say("case: cnn argument errors")
+    with pytest.raises(T.TfanError):
+        T.Cnn(1, 40, 32)
+    net = T.Cnn(1, 16, 16)
+    X = torch.zeros((2, 7, 16, 16), device="cuda")
+    with pytest.raises(T.TfanError) as e:
+        net.gradients(X, X, [0])
+    assert e.value.code == T.TFAN_EINVAL
+    tr = T.Cnn(1, 16, 16, train=True)
+    with pytest.raises(T.TfanError):
+        tr.gradients(X, X, [5])
+    with pytest.raises(T.TfanError):
+        tr.set_scales([1, 1, 1, 0, 1, 1, 1], np.ones(7))

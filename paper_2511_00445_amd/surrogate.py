@@ -8,7 +8,10 @@ the HIP library:
   on the device every k steps give training pairs (x_t, x_{t+k}).
 - channel_scales: input scales (RMS of each state channel) and output scales
   (RMS of each channel's k-step increment) from a sample of pairs.
-- train: Adam on random mini-batches of the pairs.
+- train: Adam on random mini-batches of the pairs; with max_unroll > 0 part of
+  every batch starts from the network's own predictions (pushforward): the
+  input is the network applied m times to x_t, the target the solver state at
+  t + (m + 1) k, so the network learns to correct the drift of its own rollouts.
 - SurrogateRun: advances a solver by surrogate calls of k steps; every
   check_every-th call also runs the solver over the same k steps from the same
   state, measures the surrogate's relative L2 error on (phi, Qxx, Qxy) and
@@ -26,6 +29,7 @@ from .binding import Cnn, Sim
 from .workloads import initial_fields
 
 K_STEPS = 50
+RELAX_STEPS = 25   # solver steps after each jump in the deploy loop
 
 
 def trajectory_pairs(params: dict, seeds, t0: int, t1: int, k: int = K_STEPS, phi_mean: float = 0.0):
@@ -77,15 +81,40 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 
 def train(net: Cnn, X, T, steps: int, lr: float = 1e-3, lr_final: float = 1e-4, seed: int = 0,
-          log_every: int = 0, log=print):
-    """Adam on random batches of net.batch pairs; learning rate decays
-    geometrically from lr to lr_final.  Returns the loss of every step."""
+          log_every: int = 0, log=print, per_traj: int = 0, max_unroll: int = 0, unroll_from: float = 0.3):
+    """Adam on random batches of net.batch pairs; the learning rate decays
+    geometrically from lr to lr_final.  With max_unroll > 0 (pairs stored as
+    consecutive runs of per_traj pairs per trajectory), after the first
+    unroll_from share of the steps each batch draws an unroll depth m in
+    [0, max_unroll]: inputs are the network applied m times to x_t (no gradient
+    through those applications), targets the trajectory state k (m + 1) steps
+    after t.  Returns the loss of every step."""
+    import torch
     rng = np.random.default_rng(seed)
     losses = []
+    B = net.batch
+    if max_unroll:
+        if per_traj <= max_unroll or X.shape[0] % per_traj:
+            raise ValueError("pairs must come as runs of per_traj > max_unroll pairs")
+        xa = torch.empty((B,) + tuple(X.shape[1:]), dtype=X.dtype, device=X.device)
+        xb, tt = torch.empty_like(xa), torch.empty_like(xa)
+        ids = np.arange(B, dtype=np.int32)
     for i in range(steps):
         rate = lr * (lr_final / lr) ** (i / max(1, steps - 1))
-        idx = rng.choice(X.shape[0], size=net.batch, replace=False)
-        losses.append(net.train_step(X, T, idx, rate))
+        m = int(rng.integers(0, max_unroll + 1)) if max_unroll and i >= unroll_from * steps else 0
+        if m == 0:
+            idx = rng.choice(X.shape[0], size=B, replace=False)
+            losses.append(net.train_step(X, T, idx, rate))
+        else:
+            traj = rng.integers(0, X.shape[0] // per_traj, size=B)
+            j = rng.integers(0, per_traj - m, size=B)
+            start = traj * per_traj + j
+            xa.copy_(X[torch.as_tensor(start, device=X.device)])
+            tt.copy_(T[torch.as_tensor(start + m, device=X.device)])
+            for _ in range(m):
+                net.forward(xa, xb)
+                xa, xb = xb, xa
+            losses.append(net.train_step(xa, tt, ids, rate))
         if log_every and (i + 1) % log_every == 0:
             log(f"train step {i + 1}: loss {np.mean(losses[-log_every:]):.5f} (lr {rate:.2e})")
     return losses
@@ -111,13 +140,16 @@ class SurrogateRun:
     """A solver advanced by surrogate calls, checked against itself, with rollback."""
 
     def __init__(self, sim: Sim, net: Cnn, k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2,
-                 hold: int = 10, channels=(0, 1, 2)):
+                 hold: int = 10, channels=(0, 1, 2), relax: int = 0):
         import torch
         if net.batch != 1 or (net.ny, net.nx) != (sim.ny, sim.nx):
             raise ValueError("the network must take one sample of the solver's grid")
         self.sim, self.net, self.k = sim, net, int(k)
         self.check_every, self.tol, self.hold = int(check_every), float(tol), int(hold)
         self.channels = list(channels)
+        self.relax = int(relax)  # solver steps after every call: a call covers k + relax steps
+        if self.relax < 0:
+            raise ValueError("relax must be >= 0")
         shape = (1, 7, sim.ny, sim.nx)
         self.x = torch.empty(shape, dtype=torch.float32, device="cuda")
         self.xp = torch.empty_like(self.x)
@@ -135,15 +167,15 @@ class SurrogateRun:
         self.since_check = 0
 
     def advance(self, steps: int):
-        """Advance by `steps` (a multiple of k) lattice steps."""
-        if steps % self.k:
-            raise ValueError("steps must be a multiple of k")
+        """Advance by `steps` lattice steps (a multiple of k + relax)."""
+        if steps % (self.k + self.relax):
+            raise ValueError("steps must be a multiple of k + relax")
         target = self.sim.step_count() + steps
         if self.good_step is None:
             self._mark_good()
         while self.sim.step_count() < target:
             if self.plain_left > 0:
-                self.sim.step(self.k)
+                self.sim.step(self.k + self.relax)
                 self.solver_calls += 1
                 self.plain_left -= 1
                 if self.plain_left == 0:
@@ -161,25 +193,98 @@ class SurrogateRun:
                 self.checks += 1
                 self.solver_calls += 1
                 if np.isfinite(err) and err <= self.tol:
-                    self.good.copy_(self.xs)
-                    self.good_step = self.sim.step_count()
-                    self.since_check = 0
+                    if self.relax:
+                        self.sim.step(self.relax)
+                    self._mark_good()
                 else:
                     # restore the last checked state; redo the span with the solver
-                    span = (self.sim.step_count() - self.good_step) // self.k
                     self.fallbacks += 1
+                    span = (self.sim.step_count() - self.good_step) // (self.k + self.relax) + 1
                     self.sim.import_state(self.good[0], self.good_step)
-                    self.plain_left = min(span, (target - self.good_step) // self.k) + self.hold
+                    self.plain_left = span + self.hold
                     self.since_check = 0
             else:
                 self.sim.import_state(self.xp[0], self.sim.step_count() + self.k)
                 self.surrogate_calls += 1
+                if self.relax:  # the solver smooths what the jump leaves at the grid scale
+                    self.sim.step(self.relax)
 
     def summary(self) -> dict:
         errs = [e for _, e in self.errors]
         return dict(surrogate_calls=self.surrogate_calls, solver_calls=self.solver_calls, checks=self.checks,
                     fallbacks=self.fallbacks, max_check_error=max(errs) if errs else None,
                     mean_check_error=float(np.mean(errs)) if errs else None)
+
+
+def train_surrogate(params: dict, seeds, t0: int, t1: int, steps: int, batch: int = 8, k: int = K_STEPS,
+                    lr: float = 1e-3, lr_final: float = 1e-5, seed: int = 0, velocity_weight: float = 1.0 / 9.0,
+                    max_unroll: int = 0, log=None):
+    """Pairs from solver trajectories of `params`, scales, and a trained network.
+    velocity_weight scales the loss of the four velocity channels (through
+    their output scales); the deploy checks judge (phi, Q).
+    Returns (theta, s_in, s_out, losses, seconds of training)."""
+    X, T = trajectory_pairs(params, seeds, t0, t1, k)
+    s_in, s_out = channel_scales(X, T, samples=32, seed=seed)
+    s_out[3:] /= np.float32(np.sqrt(velocity_weight))
+    net = Cnn(batch, int(params["ny"]), int(params["nx"]), train=True)
+    net.set_params(init_params(seed))
+    net.set_scales(s_in, s_out)
+    losses, secs = timed(train, net, X, T, steps, lr, lr_final, seed, (steps // 10) if log else 0,
+                         log or print, per_traj=(t1 - t0) // k, max_unroll=max_unroll)
+    theta = net.get_params()
+    net.close()
+    del X, T
+    return theta, s_in, s_out, losses, secs
+
+
+def deploy_compare(params: dict, seed: int, theta, s_in, s_out, t_start: int, t_end: int, every: int,
+                   k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2, hold: int = 10, relax: int = 0,
+                   log=None):
+    """The plain solver and the surrogate-accelerated run from the same state at
+    t_start to t_end.  Domain length L(t) every `every` steps (host analysis of phi,
+    outside the timed spans).  Returns a dict of the two L records, the stepping
+    wall times, simulated steps per second and the maximum relative L deviation."""
+    from .analysis import domain_length
+    ny, nx = int(params["ny"]), int(params["nx"])
+    sim = Sim(params)
+    sim.init_fields(**initial_fields(nx, ny, seed=int(seed)))
+    sim.step(t_start)
+    sim.sync()
+    start = sim.get_state()
+
+    def phi_length():
+        f = sim.get_fields()
+        return domain_length(f["phi"])
+
+    plain_L, plain_s = [], 0.0
+    for _ in range((t_end - t_start) // every):
+        _, dt = timed(sim.step, every)
+        plain_s += dt
+        plain_L.append(phi_length())
+    if sim.diagnostics()["status"] != 0:
+        raise RuntimeError("plain run became unhealthy")
+    sim.set_state(start)
+    net = Cnn(1, ny, nx)
+    net.set_params(theta)
+    net.set_scales(s_in, s_out)
+    run = SurrogateRun(sim, net, k=k, check_every=check_every, tol=tol, hold=hold, relax=relax)
+    sur_L, sur_s = [], 0.0
+    for _ in range((t_end - t_start) // every):
+        _, dt = timed(run.advance, every)
+        sur_s += dt
+        sur_L.append(phi_length())
+        if log:
+            log(f"step {sim.step_count()}: L plain {plain_L[len(sur_L) - 1]:.3f} surrogate {sur_L[-1]:.3f}")
+    status = sim.diagnostics()["status"]
+    dev = np.abs(np.array(sur_L) - np.array(plain_L)) / np.array(plain_L)
+    span = t_end - t_start
+    out = dict(t=list(range(t_start + every, t_end + 1, every)), L_plain=plain_L, L_surrogate=sur_L,
+               max_L_dev=float(dev.max()), plain_seconds=plain_s, surrogate_seconds=sur_s,
+               plain_steps_per_s=span / plain_s, surrogate_steps_per_s=span / sur_s, speedup=plain_s / sur_s,
+               status=status, **run.summary())
+    net.close()
+    sim.close()
+    return out
 
 
 def timed(fn, *args, **kw):

@@ -171,10 +171,11 @@ int tfan_kernel_count(void);
 const char* tfan_kernel_name(int id);
 
 /* Launch shape of the hot kernels: collide_rows in {1, 2} rows of sites per
- * thread of the collision kernel; fd_shape in {1, 2, 4}: one launch per
- * finite-difference sub-step with that many rows per thread, or in {16, 32}: all
- * n_sub sub-steps of a step in one launch on 64 x fd_shape tiles (temporal
- * blocking; used when n_sub <= 5, otherwise the 4-row per-sub-step launch runs).
+ * thread of the collision kernel; fd_shape selects the finite-difference
+ * launches: 1, 2, 4: one launch per sub-step with that many rows per thread;
+ * 16, 32: all n_sub sub-steps of a step in one launch on 64 x fd_shape tiles
+ * (temporal blocking; for n_sub > 5 the 4-row per-sub-step launch runs);
+ * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles.
  * Default (2, 16).  Results are bitwise identical for every shape; only the speed
  * differs.  Other values: TFAN_EINVAL. */
 int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape);

@@ -3,6 +3,7 @@
 // event-based kernel timing.
 #include "tfan.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -192,21 +193,24 @@ int download(tfan_sim* s, double* dst, const float* src, size_t count, std::vect
 
 }  // namespace
 
+static const int kFdShapes[] = {1, 2, 4, 16, 32, 162, 163};
 static bool valid_shape(int32_t collide_rows, int32_t fd_shape) {
-  return (collide_rows == 1 || collide_rows == 2) &&
-         (fd_shape == 1 || fd_shape == 2 || fd_shape == 4 || fd_shape == 16 || fd_shape == 32);
+  if (collide_rows != 1 && collide_rows != 2) return false;
+  for (int f : kFdShapes)
+    if (f == fd_shape) return true;
+  return false;
 }
-static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16 or 32";
-// Shapes the autotuners try: every collide_rows with every fd_shape (the fused
-// shapes only where n_sub allows them).
+static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16, 32, 162 or 163";
+// Shapes the autotuners try: every collide_rows with every fd_shape, skipping
+// blocked shapes that n_sub turns into the per-sub-step launch.
 static std::vector<tfan::Tuning> tuning_candidates(int n_sub) {
   std::vector<tfan::Tuning> out;
   for (int c : {1, 2})
-    for (int f : {1, 2, 4, 16, 32}) {
+    for (int f : kFdShapes) {
       tfan::Tuning t;
       t.collide_rows = c;
       t.fd_shape = f;
-      if (f < 16 || tfan::fd_fused(t, n_sub)) out.push_back(t);
+      if (f < 16 || tfan::fd_block(t, n_sub) > 1) out.push_back(t);
     }
   return out;
 }
@@ -294,20 +298,17 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
       hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->tune, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "collide kernel launch");
     }
-    // sub-steps alternate the phi/Q buffers; the collision above already read state a
+    // finite-difference launches alternate the phi/Q buffers; the collision above
+    // already read state a
     int src = a;
-    if (tfan::fd_fused(s->tune, s->dp.n_sub)) {
-      TimedLaunch t(s, tfan::K_FDN);
-      hipError_t e = tfan::launch_fd(s->dp, state_of(s, a), state_of(s, b), s->U, s->tune, s->stream);
+    const int block = tfan::fd_block(s->tune, s->dp.n_sub);
+    for (int done = 0; done < s->dp.n_sub;) {
+      const int subs = std::min(block, s->dp.n_sub - done);
+      TimedLaunch t(s, block > 1 ? tfan::K_FDN : tfan::K_FD);
+      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, subs, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
-      src = b;
-    } else {
-      for (int m = 0; m < s->dp.n_sub; ++m) {
-        TimedLaunch t(s, tfan::K_FD);
-        hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, s->stream);
-        if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
-        src = 1 - src;
-      }
+      src = 1 - src;
+      done += subs;
     }
     // keep the new populations and fields under one index
     if (src != b) {
@@ -742,11 +743,13 @@ int tfan_batch_step(tfan_batch* b, int64_t nsteps) {
                                               b->stream);
     if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch collide launch: ") + hipGetErrorString(e));
     int src = b->cur;
-    const int launches = tfan::fd_fused(b->tune, b->n_sub) ? 1 : b->n_sub;
-    for (int m = 0; m < launches; ++m) {
-      e = tfan::launch_fd_batch(b->table, b->first_f, count, b->tiles_f, src, b->tune, b->n_sub, b->stream);
+    const int block = tfan::fd_block(b->tune, b->n_sub);
+    for (int done = 0; done < b->n_sub;) {
+      const int subs = std::min(block, b->n_sub - done);
+      e = tfan::launch_fd_batch(b->table, b->first_f, count, b->tiles_f, src, b->tune, b->n_sub, subs, b->stream);
       if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch sub-step launch: ") + hipGetErrorString(e));
       src = 1 - src;
+      done += subs;
     }
     const int nb = 1 - b->cur;
     if (src != nb) {

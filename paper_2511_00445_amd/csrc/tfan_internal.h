@@ -42,15 +42,24 @@ struct DevState {
 
 // Launch shape of the hot kernels (results do not depend on it):
 // collide_rows in {1, 2} rows of sites per thread; fd_shape in {1, 2, 4}: one
-// launch per sub-step with that many rows per thread, or {16, 32}: all sub-steps
-// of a step in one launch on 64 x fd_shape tiles (n_sub <= kFusedMaxSub; larger
-// n_sub falls back to one launch per sub-step with 4 rows per thread).
+// launch per finite-difference sub-step with that many rows per thread;
+// {16, 32}: all sub-steps of a step in one launch on 64 x fd_shape tiles (n_sub
+// <= kFusedMaxSub, else one launch per sub-step with 4 rows per thread);
+// {162, 163}: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles.
 constexpr int kFusedMaxSub = 5;
 struct Tuning {
   int collide_rows = 2;
   int fd_shape = 16;
 };
-inline bool fd_fused(const Tuning& tn, int n_sub) { return tn.fd_shape >= 16 && n_sub <= kFusedMaxSub; }
+// Sub-steps per finite-difference launch (1: the per-sub-step kernel).
+inline int fd_block(const Tuning& tn, int n_sub) {
+  if (tn.fd_shape == 162) return n_sub >= 2 ? 2 : 1;
+  if (tn.fd_shape == 163) return n_sub >= 3 ? 3 : (n_sub == 2 ? 2 : 1);
+  if (tn.fd_shape == 16 || tn.fd_shape == 32) return (n_sub >= 2 && n_sub <= kFusedMaxSub) ? n_sub : 1;
+  return 1;
+}
+// Tile rows of the blocked sub-step kernel.
+inline int fd_tile_rows(const Tuning& tn) { return tn.fd_shape == 32 ? 32 : 16; }
 
 // One member of a batch of independent simulations (device-resident table).
 struct BatchMember {
@@ -67,9 +76,10 @@ hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevSta
                        hipStream_t st);
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
                           Tuning tn, hipStream_t st);
-// One finite-difference sub-step, or all n_sub of them when fd_fused(tn, n_sub).
+// `subs` finite-difference sub-steps in one launch: subs = 1 with the
+// per-sub-step kernel when fd_block(tn, n_sub) == 1, else 1 <= subs <= fd_block.
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
-                     Tuning tn, hipStream_t st);
+                     Tuning tn, int subs, hipStream_t st);
 // Tiles of one member for the collision (collide = true) or sub-step kernel.
 int batch_tiles(const DevParams& P, Tuning tn, bool collide);
 // Batched launches over the tiles of all members; first[m] = first tile of member m.
@@ -77,7 +87,7 @@ hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int co
                                 bool pop16, Tuning tn, hipStream_t st);
 // (all members share n_sub)
 hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src,
-                           Tuning tn, int n_sub, hipStream_t st);
+                           Tuning tn, int n_sub, int subs, hipStream_t st);
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: drho_a, drho_p, u_a, u_p*/,
                          hipStream_t st);
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,

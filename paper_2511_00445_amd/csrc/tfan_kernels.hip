@@ -415,26 +415,28 @@ __global__ void __launch_bounds__(FD_TX * FD_TY) k_fd_batch(const BatchMember* _
 }
 
 // ---------------------------------------------------------------------------
-// All n_sub <= 5 sub-steps of a step in one launch (temporal blocking in LDS).
+// Several finite-difference sub-steps in one launch (temporal blocking in LDS).
 // The Cahn-Hilliard and Beris-Edwards sub-steps do not depend on each other, so
 // the two fields grow their halos separately: phi needs phi at distance 2 per
-// sub-step (through mu), Q needs Q at distance 1.  A block stages, for a 64 x TH
-// tile, phi and u_c with a halo of 10 and Q and u_a with a halo of 5, then runs
-// the sub-steps on boxes that shrink by 2 (phi) and 1 (Q) per sub-step, and
-// writes only the final phi and Q of its tile.  The arithmetic of each site
-// update is that of fd_tile, term for term, so both paths give the same bits.
+// sub-step (through mu), Q needs Q at distance 1.  For up to MS sub-steps a
+// block stages, for a 64 x TH tile, phi and u_c with a halo of 2 MS and Q and
+// u_a with a halo of MS, then runs the sub-steps on boxes that shrink by 2 (phi)
+// and 1 (Q) per sub-step, and writes only the final phi and Q of its tile.  The
+// arithmetic of each site update is that of fd_tile, term for term, so every
+// blocking gives the same bits.  Deeper blocking reads the fields fewer times
+// but recomputes more halo sites (MS = 5 on 64 x 16 tiles: 1.6x the sub-step
+// work; MS = 2: 1.2x).
 // ---------------------------------------------------------------------------
-constexpr int FF_X = 64, FF_MAXSUB = 5;
-constexpr int FF_HA = 2 * FF_MAXSUB;  // halo of the phi / mu / u_c frame
-constexpr int FF_HB = FF_MAXSUB;      // halo of the Q / u_a frame
-template <int TH> struct Fused {
-  static constexpr int AW = FF_X + 2 * FF_HA, AH = TH + 2 * FF_HA;
-  static constexpr int BW = FF_X + 2 * FF_HB, BH = TH + 2 * FF_HB;
+constexpr int FF_X = 64;
+template <int TH, int MS> struct Fused {
+  static constexpr int HA = 2 * MS, HB = MS;  // halos of the phi / mu / u_c and Q / u_a frames
+  static constexpr int AW = FF_X + 2 * HA, AH = TH + 2 * HA;
+  static constexpr int BW = FF_X + 2 * HB, BH = TH + 2 * HB;
   static constexpr int NT = TH >= 32 ? 1024 : 512;
   static constexpr int KA = (AW * AH + NT - 1) / NT, KB = (BW * BH + NT - 1) / NT;
-  // largest boxes updated into registers: phi with halo 2 n_sub - 2, Q with n_sub - 1
-  static constexpr int KP = ((FF_X + 4 * FF_MAXSUB - 4) * (TH + 4 * FF_MAXSUB - 4) + NT - 1) / NT;
-  static constexpr int KQ = ((FF_X + 2 * FF_MAXSUB - 2) * (TH + 2 * FF_MAXSUB - 2) + NT - 1) / NT;
+  // largest boxes updated into registers: phi with halo 2 MS - 2, Q with MS - 1
+  static constexpr int KP = ((FF_X + 4 * MS - 4) * (TH + 4 * MS - 4) + NT - 1) / NT;
+  static constexpr int KQ = ((FF_X + 2 * MS - 2) * (TH + 2 * MS - 2) + NT - 1) / NT;
 };
 template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
   return ((nx + FF_X - 1) / FF_X) * ((ny + TH - 1) / TH);
@@ -444,15 +446,17 @@ template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
 // rounded product is at least 0.5 / w away from an integer, far above its error.
 __device__ __forceinline__ int box_row(int c, float inv_w) { return (int)(((float)c + 0.5f) * inv_w); }
 
-template <int TH>
+// S (1 <= S <= MS) sub-steps from state `in` to state `out`.
+template <int TH, int MS>
 __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState& in, const DevState& out,
-                                              const float* __restrict__ U, int tile) {
-  using F = Fused<TH>;
+                                              const float* __restrict__ U, int tile, int S) {
+  using F = Fused<TH, MS>;
   constexpr int AW = F::AW, AH = F::AH, BW = F::BW, BH = F::BH, NT = F::NT;
+  constexpr int FF_HA = F::HA, FF_HB = F::HB;
   __shared__ float sphi[AH * AW], smu[AH * AW], sucx[AH * AW], sucy[AH * AW];
   __shared__ float sqx[BH * BW], sqy[BH * BW], suax[BH * BW], suay[BH * BW];
   __shared__ unsigned scol[AW], srow[AH];
-  const int nx = P.nx, ny = P.ny, n = P.n, S = P.n_sub;
+  const int nx = P.nx, ny = P.ny, n = P.n;
   const int gx = (nx + FF_X - 1) / FF_X;
   const int x0 = (tile % gx) * FF_X, y0 = (tile / gx) * TH;
   const int tid = threadIdx.x;
@@ -609,23 +613,23 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
   }
 }
 
-template <int TH>
-__global__ void __launch_bounds__(Fused<TH>::NT) k_fd_fused(DevParams P, DevState in, DevState out,
-                                                             const float* __restrict__ U) {
+template <int TH, int MS>
+__global__ void __launch_bounds__((Fused<TH, MS>::NT)) k_fd_fused(DevParams P, DevState in, DevState out,
+                                                                 const float* __restrict__ U, int subs) {
   const int tile = xcd_tile(fused_tiles<TH>(P.nx, P.ny));
   if (tile < 0) return;
-  fd_fused_tile<TH>(P, in, out, U, tile);
+  fd_fused_tile<TH, MS>(P, in, out, U, tile, subs);
 }
 
-template <int TH>
-__global__ void __launch_bounds__(Fused<TH>::NT) k_fd_fused_batch(const BatchMember* __restrict__ mem,
-                                                                   const int* __restrict__ first, int count,
-                                                                   int tiles, int src) {
+template <int TH, int MS>
+__global__ void __launch_bounds__((Fused<TH, MS>::NT)) k_fd_fused_batch(const BatchMember* __restrict__ mem,
+                                                                       const int* __restrict__ first, int count,
+                                                                       int tiles, int src, int subs) {
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int m = batch_member(first, count, tile);
   const DevParams P = mem[m].P;
-  fd_fused_tile<TH>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m]);
+  fd_fused_tile<TH, MS>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m], subs);
 }
 
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
@@ -803,14 +807,19 @@ hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u
   return hipGetLastError();
 }
 
-hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, hipStream_t st) {
-  if (fd_fused(tn, P.n_sub)) {
-    if (tn.fd_shape == 16)
-      hipLaunchKernelGGL(k_fd_fused<16>, dim3(xcd_grid(fused_tiles<16>(P.nx, P.ny))), dim3(Fused<16>::NT), 0, st,
-                         P, in, out, u);
-    else
-      hipLaunchKernelGGL(k_fd_fused<32>, dim3(xcd_grid(fused_tiles<32>(P.nx, P.ny))), dim3(Fused<32>::NT), 0, st,
-                         P, in, out, u);
+hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, int subs,
+                     hipStream_t st) {
+  const int block = fd_block(tn, P.n_sub);
+  if (block > 1) {
+    const int th = fd_tile_rows(tn);
+#define TFAN_FUSED(TH_, MS_)                                                                                  \
+  hipLaunchKernelGGL((k_fd_fused<TH_, MS_>), dim3(xcd_grid(fused_tiles<TH_>(P.nx, P.ny))),                    \
+                     dim3(Fused<TH_, MS_>::NT), 0, st, P, in, out, u, subs)
+    if (block == 2) TFAN_FUSED(16, 2);
+    else if (block == 3) TFAN_FUSED(16, 3);
+    else if (th == 16) TFAN_FUSED(16, 5);
+    else TFAN_FUSED(32, 5);
+#undef TFAN_FUSED
     return hipGetLastError();
   }
   switch (tn.fd_shape) {
@@ -823,7 +832,7 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
 
 int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
   if (collide) return tn.collide_rows == 1 ? collide_tiles<1>(P.nx, P.ny) : collide_tiles<2>(P.nx, P.ny);
-  if (fd_fused(tn, P.n_sub)) return tn.fd_shape == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
+  if (fd_block(tn, P.n_sub) > 1) return fd_tile_rows(tn) == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
   return tn.fd_shape == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_shape == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
 }
 
@@ -841,13 +850,17 @@ hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int co
 }
 
 hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, int tiles, int src, Tuning tn,
-                           int n_sub, hipStream_t st) {
+                           int n_sub, int subs, hipStream_t st) {
   const dim3 grid(xcd_grid(tiles)), blk(FD_TX, FD_TY);
-  if (fd_fused(tn, n_sub)) {
-    if (tn.fd_shape == 16)
-      hipLaunchKernelGGL(k_fd_fused_batch<16>, grid, dim3(Fused<16>::NT), 0, st, mem, first, count, tiles, src);
-    else
-      hipLaunchKernelGGL(k_fd_fused_batch<32>, grid, dim3(Fused<32>::NT), 0, st, mem, first, count, tiles, src);
+  const int block = fd_block(tn, n_sub);
+  if (block > 1) {
+#define TFAN_FUSED_B(TH_, MS_) \
+  hipLaunchKernelGGL((k_fd_fused_batch<TH_, MS_>), grid, dim3(Fused<TH_, MS_>::NT), 0, st, mem, first, count, tiles, src, subs)
+    if (block == 2) TFAN_FUSED_B(16, 2);
+    else if (block == 3) TFAN_FUSED_B(16, 3);
+    else if (fd_tile_rows(tn) == 16) TFAN_FUSED_B(16, 5);
+    else TFAN_FUSED_B(32, 5);
+#undef TFAN_FUSED_B
     return hipGetLastError();
   }
   switch (tn.fd_shape) {

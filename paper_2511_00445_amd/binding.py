@@ -113,6 +113,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_cnn_sync": (ctypes.c_int, [_vp]),
         "tfan_cnn_destroy": (None, [_vp]),
         "tfan_cnn_last_error": (ctypes.c_char_p, [_vp]),
+        "tfan_analysis_shells": (ctypes.c_int32, [ctypes.c_int32]),
+        "tfan_analysis_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+        "tfan_analysis_create": (ctypes.c_int, [ctypes.c_int32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+        "tfan_analysis_spectra": (ctypes.c_int, [_vp, _vp, _dp, _dp, _dp, _dp, _dp]),
+        "tfan_analysis_correlations": (ctypes.c_int, [_vp, _vp, _dp, _dp, _dp, _dp]),
+        "tfan_analysis_overlaps": (ctypes.c_int, [_vp, _vp, _vp, _dp]),
+        "tfan_analysis_defects": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int64), _P(ctypes.c_int64)]),
+        "tfan_analysis_sync": (ctypes.c_int, [_vp]),
+        "tfan_analysis_destroy": (None, [_vp]),
+        "tfan_analysis_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_destroy": (None, [_vp]),
         "tfan_last_error": (ctypes.c_char_p, [_vp]),
     }
@@ -491,6 +501,73 @@ class Cnn:
     def close(self):
         if getattr(self, "_handle", None):
             self.lib.tfan_cnn_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Analysis:
+    """On-device observables (include/tfan_analysis.h) of exported states
+    [7][n][n] (float32 device tensors) on an n x n grid, n a power of two."""
+
+    def __init__(self, n: int, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible: the analysis runs only on the GPU")
+        self.lib = load_library()
+        self.n = int(n)
+        nbytes = int(self.lib.tfan_analysis_workspace_bytes(self.n))
+        if nbytes == 0:
+            raise TfanError(TFAN_EINVAL, "n must be a power of two in [8, 4096]")
+        self.shells = int(self.lib.tfan_analysis_shells(self.n))
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        aligned = (self.workspace.data_ptr() + 255) // 256 * 256
+        self._handle = _vp()
+        rc = self.lib.tfan_analysis_create(self.n, _vp(aligned), nbytes, _vp(self.stream.cuda_stream),
+                                           ctypes.byref(self._handle))
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_analysis_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != TFAN_OK:
+            raise TfanError(rc, self.lib.tfan_analysis_last_error(self._handle).decode())
+
+    def _state(self, x):
+        _check_dev(x, (7, self.n, self.n))
+        return _vp(x.data_ptr())
+
+    def spectra(self, x) -> dict:
+        out = {k: np.empty(self.shells) for k in ("E", "W", "S", "count")}
+        L = ctypes.c_double()
+        self._check(self.lib.tfan_analysis_spectra(self._handle, self._state(x), _ptr(out["E"]), _ptr(out["W"]),
+                                                   _ptr(out["S"]), _ptr(out["count"]), ctypes.byref(L)))
+        out["L"] = L.value
+        return out
+
+    def correlations(self, x) -> dict:
+        out = {k: np.empty(self.shells) for k in ("uu", "ww", "QQ", "count")}
+        self._check(self.lib.tfan_analysis_correlations(self._handle, self._state(x), _ptr(out["uu"]),
+                                                        _ptr(out["ww"]), _ptr(out["QQ"]), _ptr(out["count"])))
+        return out
+
+    def overlaps(self, x0, x1) -> np.ndarray:
+        out = np.empty(6)
+        self._check(self.lib.tfan_analysis_overlaps(self._handle, self._state(x0), self._state(x1), _ptr(out)))
+        return out
+
+    def defects(self, x) -> tuple:
+        p, m = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tfan_analysis_defects(self._handle, self._state(x), ctypes.byref(p), ctypes.byref(m)))
+        return p.value, m.value
+
+    def close(self):
+        if getattr(self, "_handle", None):
+            self.lib.tfan_analysis_destroy(self._handle)
             self._handle = None
 
     def __del__(self):

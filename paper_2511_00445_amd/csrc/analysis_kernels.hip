@@ -1,0 +1,344 @@
+// gfx950 kernels of the on-device observables (Results section): packing of the
+// exported state into complex fields, a radix-2 2D FFT (one row per block in LDS,
+// tiled transposes), power spectra, shell sums, spatial-correlation maps,
+// temporal-correlation overlaps and the winding-number defect count.
+#include "analysis_internal.h"
+
+namespace tana {
+namespace {
+
+__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Nearest integer to sqrt(m2) for an integer m2 >= 0, exactly: (s + 1/2)^2 =
+// s^2 + s + 1/4, so the nearest integer is s + 1 once m2 >= s^2 + s + 1.
+__device__ __forceinline__ int shell_of(int m2) {
+  int s = (int)sqrtf((float)m2);
+  while (s * s > m2) --s;
+  while ((s + 1) * (s + 1) <= m2) ++s;
+  return (m2 >= s * s + s + 1) ? s + 1 : s;
+}
+// Signed frequency (or minimum-image displacement) of index i; only |.| is used.
+__device__ __forceinline__ int freq(int i, int n) { return i <= n / 2 ? i : i - n; }
+
+// Mixed velocity u_c = c1 u_a + c2 u_p at site (y, x) of an exported state.
+__device__ __forceinline__ float2 mixed(const float* __restrict__ s, size_t n2, int idx) {
+  const float c1 = 0.5f * (1.f + s[idx]);
+  const float c2 = 1.f - c1;
+  return make_float2(c1 * s[3 * n2 + idx] + c2 * s[5 * n2 + idx], c1 * s[4 * n2 + idx] + c2 * s[6 * n2 + idx]);
+}
+// Mixed vorticity d_x u_c,y - d_y u_c,x (central differences) at (y, x).
+__device__ __forceinline__ float vort(const float* __restrict__ s, int n, int y, int x) {
+  const size_t n2 = (size_t)n * n;
+  const float2 e = mixed(s, n2, y * n + wrapn(x + 1, n)), w = mixed(s, n2, y * n + wrapn(x - 1, n));
+  const float2 no = mixed(s, n2, wrapn(y + 1, n) * n + x), so = mixed(s, n2, wrapn(y - 1, n) * n + x);
+  return 0.5f * (e.y - w.y) - 0.5f * (no.x - so.x);
+}
+
+// za = phi + i omega_c, zb = u_c,x + i u_c,y, zc = Qxx + i Qxy.
+__global__ void k_pack(const float* __restrict__ s, int n, float2* __restrict__ za, float2* __restrict__ zb,
+                       float2* __restrict__ zc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int y = i / n, x = i - y * n;
+  const size_t n2 = (size_t)n * n;
+  const float2 u = mixed(s, n2, i);
+  za[i] = make_float2(s[i], vort(s, n, y, x));
+  zb[i] = u;
+  zc[i] = make_float2(s[n2 + i], s[2 * n2 + i]);
+}
+
+// Radix-2 FFT of every row (one block per row): bit-reversed load into LDS, then
+// log2(n) butterfly stages with twiddles w_k = exp(-+ 2 pi i k / n) from a table.
+// Unnormalised; INV uses the conjugate twiddles.
+template <bool INV>
+__global__ void __launch_bounds__(256) k_fft_rows(float2* __restrict__ data, int n, int logn) {
+  extern __shared__ float2 sm[];
+  float2* buf = sm;
+  float2* tw = sm + n;
+  float2* row = data + (size_t)blockIdx.x * n;
+  for (int i = threadIdx.x; i < n; i += 256) buf[__brev((unsigned)i) >> (32 - logn)] = row[i];
+  for (int k = threadIdx.x; k < n / 2; k += 256) {
+    float sn, cs;
+    sincospif(2.f * (float)k / (float)n, &sn, &cs);
+    tw[k] = make_float2(cs, INV ? sn : -sn);
+  }
+  __syncthreads();
+  for (int lh = 0; lh < logn; ++lh) {
+    const int half = 1 << lh, stride = n >> (lh + 1);
+    for (int b = threadIdx.x; b < n / 2; b += 256) {
+      const int pos = b & (half - 1), grp = b >> lh;
+      const int i = (grp << (lh + 1)) + pos, j = i + half;
+      const float2 w = tw[pos * stride], v = buf[j], u = buf[i];
+      const float2 t = make_float2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+      buf[i] = make_float2(u.x + t.x, u.y + t.y);
+      buf[j] = make_float2(u.x - t.x, u.y - t.y);
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += 256) row[i] = buf[i];
+}
+
+// out = in^T, 32 x 32 tiles through LDS (32 x 8 threads).
+__global__ void k_transpose(const float2* __restrict__ in, float2* __restrict__ out, int n) {
+  __shared__ float2 t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int j = threadIdx.y; j < 32; j += 8)
+    if (by + j < n && bx + (int)threadIdx.x < n) t[j][threadIdx.x] = in[(size_t)(by + j) * n + bx + threadIdx.x];
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += 8)
+    if (bx + j < n && by + (int)threadIdx.x < n) out[(size_t)(bx + j) * n + by + threadIdx.x] = t[threadIdx.x][j];
+}
+
+// From the transforms of za, zb, zc (natural layout): pE = |hat u_c|^2 / 2,
+// pS = |hat phi|^2 (hat = FFT / n^2), and the inverse inputs
+// w0 = (|hat du|^2, |hat dw|^2) (k = 0 removed: fluctuations), w1 = (|hat Q|^2, 0).
+// With Z = FFT(a + i b) for real a, b: hat a = (Z(k) + conj Z(-k)) / 2,
+// hat b = (Z(k) - conj Z(-k)) / 2i, |hat a|^2 + |hat b|^2 = (|Z(k)|^2 + |Z(-k)|^2) / 2.
+__global__ void k_power(const float2* __restrict__ za, const float2* __restrict__ zb, const float2* __restrict__ zc,
+                        int n, float inv_n4, float* __restrict__ pE, float* __restrict__ pS,
+                        float2* __restrict__ w0, float2* __restrict__ w1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  const int a = i / n, b = i - a * n;
+  const int m = ((n - a) & (n - 1)) * n + ((n - b) & (n - 1));
+  const float2 A = za[i], Am = za[m];
+  const float px = 0.5f * (A.x + Am.x), py = 0.5f * (A.y - Am.y);     // hat phi * n^2
+  const float ox = 0.5f * (A.y + Am.y), oy = -0.5f * (A.x - Am.x);    // hat omega * n^2
+  const float2 B = zb[i], Bm = zb[m], Cq = zc[i], Cm = zc[m];
+  const float pu = 0.5f * ((B.x * B.x + B.y * B.y) + (Bm.x * Bm.x + Bm.y * Bm.y)) * inv_n4;
+  const float pw = (ox * ox + oy * oy) * inv_n4;
+  const float pq = 0.5f * ((Cq.x * Cq.x + Cq.y * Cq.y) + (Cm.x * Cm.x + Cm.y * Cm.y)) * inv_n4;
+  pE[i] = 0.5f * pu;
+  pS[i] = (px * px + py * py) * inv_n4;
+  w0[i] = i == 0 ? make_float2(0.f, 0.f) : make_float2(pu, pw);
+  w1[i] = make_float2(pq, 0.f);
+}
+
+// Per-row shell sums (one thread per row, fixed order): partial[c][row][s] for up
+// to three inputs (element e of input c at in_c[stride_c * e]) and the count of
+// elements per shell and row.
+__global__ void k_shell_rows(const float* __restrict__ in0, const float* __restrict__ in1,
+                             const float* __restrict__ in2, int stride, int n, int ns,
+                             double* __restrict__ partial, int* __restrict__ pcount) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const size_t plane = (size_t)n * ns;
+  double* p0 = partial + (size_t)row * ns;
+  int* pc = pcount + (size_t)row * ns;
+  for (int s = 0; s < ns; ++s) {
+    p0[s] = 0.0;
+    p0[plane + s] = 0.0;
+    p0[2 * plane + s] = 0.0;
+    pc[s] = 0;
+  }
+  const int fy = freq(row, n);
+  for (int i = 0; i < n; ++i) {
+    const int fx = freq(i, n);
+    const int s = shell_of(fx * fx + fy * fy);
+    const size_t e = (size_t)stride * ((size_t)row * n + i);
+    if (in0) p0[s] += (double)in0[e];
+    if (in1) p0[plane + s] += (double)in1[e];
+    if (in2) p0[2 * plane + s] += (double)in2[e];
+    pc[s] += 1;
+  }
+}
+
+// Sum of the row partials in row order; norm_c = value at the origin of input c
+// (correlation maps; 0: no normalisation, and no division by the count).
+__global__ void k_shell_reduce(const double* __restrict__ partial, const int* __restrict__ pcount, int n, int ns,
+                               const float* __restrict__ in0, const float* __restrict__ in1,
+                               const float* __restrict__ in2, int mean, double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  const size_t plane = (size_t)n * ns;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  long long c = 0;
+  for (int r = 0; r < n; ++r) {
+    const size_t o = (size_t)r * ns + s;
+    a0 += partial[o];
+    a1 += partial[plane + o];
+    a2 += partial[2 * plane + o];
+    c += pcount[o];
+  }
+  if (mean) {  // correlation maps: divide by the value at r = 0 and by the count
+    a0 = in0 ? a0 / ((double)in0[0] * (double)c) : 0.0;
+    a1 = in1 ? a1 / ((double)in1[0] * (double)c) : 0.0;
+    a2 = in2 ? a2 / ((double)in2[0] * (double)c) : 0.0;
+  }
+  out[s] = a0;
+  out[ns + s] = a1;
+  out[2 * ns + s] = a2;
+  out[3 * ns + s] = (double)c;
+}
+
+// W(s) = k_s^2 E(s) and L from E = out[0..ns), S = out[ns..2ns); writes W into
+// out[2ns..3ns) and L into out[4ns].
+__global__ void k_finish_spectra(double* __restrict__ out, int n, int ns) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double two_pi_n = 2.0 * 3.14159265358979323846 / (double)n;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < ns; ++s) {
+    const double k = two_pi_n * s;
+    out[2 * ns + s] = k * k * out[s];
+    if (s > 0) {
+      num += out[ns + s];
+      den += k * out[ns + s];
+    }
+  }
+  out[4 * ns] = 2.0 * 3.14159265358979323846 * num / den;
+}
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Per-block sums of the six temporal-correlation products.
+__global__ void __launch_bounds__(kRedThreads) k_overlaps(const float* __restrict__ s0, const float* __restrict__ s1,
+                                                          int n, double* __restrict__ partial) {
+  __shared__ double red[kRedThreads / 64];
+  const size_t n2 = (size_t)n * n;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = blockIdx.x * kRedThreads + threadIdx.x; i < n * n; i += gridDim.x * kRedThreads) {
+    const int y = i / n, x = i - y * n;
+    const float2 ua = mixed(s0, n2, i), ub = mixed(s1, n2, i);
+    const float wa = vort(s0, n, y, x), wb = vort(s1, n, y, x);
+    acc[0] += (double)ua.x * ub.x + (double)ua.y * ub.y;
+    acc[1] += (double)ua.x * ua.x + (double)ua.y * ua.y;
+    acc[2] += (double)wa * wb;
+    acc[3] += (double)wa * wa;
+    acc[4] += 2.0 * ((double)s0[n2 + i] * s1[n2 + i] + (double)s0[2 * n2 + i] * s1[2 * n2 + i]);
+    acc[5] += 2.0 * ((double)s0[n2 + i] * s0[n2 + i] + (double)s0[2 * n2 + i] * s0[2 * n2 + i]);
+  }
+  for (int k = 0; k < 6; ++k) {
+    const double t = block_sum(acc[k], red);
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * 6 + k] = t;
+  }
+}
+
+__global__ void k_overlaps_final(const double* __restrict__ partial, int nblk, double inv_sites,
+                                 double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k >= 6) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * 6 + k];
+  out[k] = s * inv_sites;
+}
+
+// +-1/2 defects by winding number around every plaquette (float32 decisions).
+__device__ __forceinline__ float wrap_half(float d) {
+  const float hp = 1.57079632679489662f, pi = 3.14159265358979324f;
+  d = d >= hp ? d - pi : d;
+  return d < -hp ? d + pi : d;
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_defects(const float* __restrict__ s, int n,
+                                                         long long* __restrict__ partial) {
+  __shared__ double red[kRedThreads / 64];
+  const size_t n2 = (size_t)n * n;
+  double plus = 0.0, minus = 0.0;  // integer counts carried exactly in doubles (< 2^53)
+  for (int i = blockIdx.x * kRedThreads + threadIdx.x; i < n * n; i += gridDim.x * kRedThreads) {
+    const int y = i / n, x = i - y * n;
+    const int x1 = wrapn(x + 1, n), y1 = wrapn(y + 1, n);
+    const int i10 = y * n + x1, i11 = y1 * n + x1, i01 = y1 * n + x;
+    const float t00 = 0.5f * atan2f(s[2 * n2 + i], s[n2 + i]);
+    const float t10 = 0.5f * atan2f(s[2 * n2 + i10], s[n2 + i10]);
+    const float t11 = 0.5f * atan2f(s[2 * n2 + i11], s[n2 + i11]);
+    const float t01 = 0.5f * atan2f(s[2 * n2 + i01], s[n2 + i01]);
+    const float w = ((wrap_half(t10 - t00) + wrap_half(t11 - t10)) + wrap_half(t01 - t11)) + wrap_half(t00 - t01);
+    if (w > 1.57079632679489662f) plus += 1.0;
+    if (w < -1.57079632679489662f) minus += 1.0;
+  }
+  const double p = block_sum(plus, red);
+  const double m = block_sum(minus, red);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = (long long)p;
+    partial[2 * blockIdx.x + 1] = (long long)m;
+  }
+}
+
+__global__ void k_defects_final(const long long* __restrict__ partial, int nblk, long long* __restrict__ out) {
+  if (threadIdx.x > 1) return;
+  long long s = 0;
+  for (int b = 0; b < nblk; ++b) s += partial[2 * b + threadIdx.x];
+  out[threadIdx.x] = s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_pack(const float* s, int n, float2* za, float2* zb, float2* zc, hipStream_t st) {
+  const int n2 = n * n;
+  hipLaunchKernelGGL(k_pack, dim3((n2 + 255) / 256), dim3(256), 0, st, s, n, za, zb, zc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft2(float2* z, float2* scratch, int n, int logn, bool inverse, hipStream_t st) {
+  const size_t lds = (size_t)n * sizeof(float2) + (size_t)(n / 2) * sizeof(float2);
+  const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
+  for (int pass = 0; pass < 2; ++pass) {
+    float2* src = pass == 0 ? z : scratch;
+    float2* dst = pass == 0 ? scratch : z;
+    if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, src, n, logn);
+    else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, src, n, logn);
+    hipLaunchKernelGGL(k_transpose, tg, tb, 0, st, src, dst, n);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, int n, float* pE, float* pS,
+                        float2* w0, float2* w1, hipStream_t st) {
+  const double n4 = (double)n * n * (double)n * n;
+  const int n2 = n * n;
+  hipLaunchKernelGGL(k_power, dim3((n2 + 255) / 256), dim3(256), 0, st, za, zb, zc, n, (float)(1.0 / n4), pE, pS,
+                     w0, w1);
+  return hipGetLastError();
+}
+
+hipError_t launch_shells(const float* in0, const float* in1, const float* in2, int stride, int n, int ns, bool mean,
+                         double* partial, int* pcount, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_shell_rows, dim3((n + 63) / 64), dim3(64), 0, st, in0, in1, in2, stride, n, ns, partial,
+                     pcount);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_shell_reduce, dim3((ns + 63) / 64), dim3(64), 0, st, partial, pcount, n, ns, in0, in1, in2,
+                     mean ? 1 : 0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_spectra(double* out, int n, int ns, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_spectra, dim3(1), dim3(64), 0, st, out, n, ns);
+  return hipGetLastError();
+}
+
+int reduce_blocks(int n) {
+  const int b = (n * n + kRedThreads - 1) / kRedThreads;
+  return b < 1024 ? b : 1024;
+}
+
+hipError_t launch_overlaps(const float* s0, const float* s1, int n, double* partial, double* out, hipStream_t st) {
+  const int nblk = reduce_blocks(n);
+  hipLaunchKernelGGL(k_overlaps, dim3(nblk), dim3(kRedThreads), 0, st, s0, s1, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_overlaps_final, dim3(1), dim3(64), 0, st, partial, nblk, 1.0 / ((double)n * n), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_defects(const float* s, int n, long long* partial, long long* out, hipStream_t st) {
+  const int nblk = reduce_blocks(n);
+  hipLaunchKernelGGL(k_defects, dim3(nblk), dim3(kRedThreads), 0, st, s, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_defects_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+  return hipGetLastError();
+}
+
+}  // namespace tana

@@ -184,14 +184,14 @@ int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, d
 int tfan_analysis_defects(tfan_analysis* a, const float* s, int64_t* plus, int64_t* minus) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s || !plus || !minus) return fail(a, TFAN_EINVAL, "NULL argument");
-  long long* d = a->at<long long>(a->p.dout);
-  hipError_t e = tana::launch_defects(s, a->n, a->at<long long>(a->p.dpart), d, a->stream);
-  long long h[2] = {0, 0};
+  double* d = a->at<double>(a->p.dout);
+  hipError_t e = tana::launch_defects(s, a->n, a->at<double>(a->p.dpart), d, a->stream);
+  double h[2] = {0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, a->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
   if (e != hipSuccess) return hip_fail(a, e, "defects");
-  *plus = h[0];
-  *minus = h[1];
+  *plus = (int64_t)h[0];
+  *minus = (int64_t)h[1];
   return TFAN_OK;
 }
 

@@ -15,13 +15,14 @@ hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, in
                         float2* w0, float2* w1, hipStream_t st);
 // Shell sums of up to three inputs (element e at in_c[stride * e]) into out[4][ns]
 // (three sums and the counts); mean: divide by the value at the origin and by the
-// count (correlation maps).  partial: 3 n ns doubles, pcount: n ns ints.
+// count (correlation maps).  partial: 3 ns n doubles, pcount: ns n ints.
 hipError_t launch_shells(const float* in0, const float* in1, const float* in2, int stride, int n, int ns, bool mean,
                          double* partial, int* pcount, double* out, hipStream_t st);
 // W = k^2 E into out[2 ns ..) and L into out[4 ns].
 hipError_t launch_finish_spectra(double* out, int n, int ns, hipStream_t st);
 int reduce_blocks(int n);
 hipError_t launch_overlaps(const float* s0, const float* s1, int n, double* partial, double* out, hipStream_t st);
-hipError_t launch_defects(const float* state, int n, long long* partial, long long* out, hipStream_t st);
+// Defect counts (exact integers carried in doubles): out[0] = +1/2, out[1] = -1/2.
+hipError_t launch_defects(const float* state, int n, double* partial, double* out, hipStream_t st);
 
 }  // namespace tana

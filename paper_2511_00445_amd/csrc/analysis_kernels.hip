@@ -114,70 +114,103 @@ __global__ void k_power(const float2* __restrict__ za, const float2* __restrict_
   w1[i] = make_float2(pq, 0.f);
 }
 
-// Per-row shell sums (one thread per row, fixed order): partial[c][row][s] for up
-// to three inputs (element e of input c at in_c[stride_c * e]) and the count of
-// elements per shell and row.
-__global__ void k_shell_rows(const float* __restrict__ in0, const float* __restrict__ in1,
-                             const float* __restrict__ in2, int stride, int n, int ns,
-                             double* __restrict__ partial, int* __restrict__ pcount) {
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  const size_t plane = (size_t)n * ns;
-  double* p0 = partial + (size_t)row * ns;
-  int* pc = pcount + (size_t)row * ns;
-  for (int s = 0; s < ns; ++s) {
-    p0[s] = 0.0;
-    p0[plane + s] = 0.0;
-    p0[2 * plane + s] = 0.0;
-    pc[s] = 0;
-  }
-  const int fy = freq(row, n);
-  for (int i = 0; i < n; ++i) {
-    const int fx = freq(i, n);
-    const int s = shell_of(fx * fx + fy * fy);
-    const size_t e = (size_t)stride * ((size_t)row * n + i);
-    if (in0) p0[s] += (double)in0[e];
-    if (in1) p0[plane + s] += (double)in1[e];
-    if (in2) p0[2 * plane + s] += (double)in2[e];
-    pc[s] += 1;
-  }
+// Largest integer r with r * r <= v (v >= 0), exactly.
+__device__ __forceinline__ int isqrt_floor(int v) {
+  int r = (int)sqrtf((float)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
 }
 
-// Sum of the row partials in row order; norm_c = value at the origin of input c
-// (correlation maps; 0: no normalisation, and no division by the count).
-__global__ void k_shell_reduce(const double* __restrict__ partial, const int* __restrict__ pcount, int n, int ns,
-                               const float* __restrict__ in0, const float* __restrict__ in1,
-                               const float* __restrict__ in2, int mean, double* __restrict__ out) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
-  const size_t plane = (size_t)n * ns;
+// Shell sums, one thread per (shell s, row j): the sites of row j in shell s are
+// those with (s - 1/2)^2 <= fx^2 + fy^2 < (s + 1/2)^2, i.e. fx^2 in
+// [s^2 - s + 1 - fy^2, s^2 + s - fy^2] (s = 0: fx = fy = 0), an interval of |fx|
+// taken at +fx and -fx.  Each thread sums its sites in a fixed order and writes
+// partial[c][s][j] (three inputs, element e at in_c[stride * e]) and the count.
+__global__ void k_shell_part(const float* __restrict__ in0, const float* __restrict__ in1,
+                             const float* __restrict__ in2, int stride, int n, int ns,
+                             double* __restrict__ partial, int* __restrict__ pcount) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+  if (j >= n) return;
+  const int fy = freq(j, n), f2 = fy * fy, half = n / 2;
+  const int lo = s == 0 ? 0 : s * s - s + 1, hi = s == 0 ? 0 : s * s + s;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  long long c = 0;
-  for (int r = 0; r < n; ++r) {
-    const size_t o = (size_t)r * ns + s;
-    a0 += partial[o];
-    a1 += partial[plane + o];
-    a2 += partial[2 * plane + o];
-    c += pcount[o];
+  int c = 0;
+  if (f2 <= hi) {
+    const int b2 = hi - f2, a2lim = lo > f2 ? lo - f2 : 0;
+    int fa = isqrt_floor(a2lim);
+    if (fa * fa < a2lim) ++fa;  // ceil
+    int fb = isqrt_floor(b2);
+    if (fb > half) fb = half;
+    const size_t row = (size_t)j * n;
+    for (int fx = fa; fx <= fb; ++fx) {
+      for (int sign = 0; sign < 2; ++sign) {
+        if (sign == 1 && (fx == 0 || fx == half)) continue;  // +fx and -fx are one bin
+        const size_t e = (size_t)stride * (row + (sign ? n - fx : fx));
+        if (in0) a0 += (double)in0[e];
+        if (in1) a1 += (double)in1[e];
+        if (in2) a2 += (double)in2[e];
+        ++c;
+      }
+    }
   }
-  if (mean) {  // correlation maps: divide by the value at r = 0 and by the count
-    a0 = in0 ? a0 / ((double)in0[0] * (double)c) : 0.0;
-    a1 = in1 ? a1 / ((double)in1[0] * (double)c) : 0.0;
-    a2 = in2 ? a2 / ((double)in2[0] * (double)c) : 0.0;
+  const size_t plane = (size_t)ns * n, o = (size_t)s * n + j;
+  partial[o] = a0;
+  partial[plane + o] = a1;
+  partial[2 * plane + o] = a2;
+  pcount[o] = c;
+}
+
+// Sum over rows of every shell (one block per shell, fixed strided assignment and
+// fixed tree); mean: divide by the value at the origin of the input and by the
+// count (correlation maps).
+__global__ void __launch_bounds__(256) k_shell_sum(const double* __restrict__ partial, const int* __restrict__ pcount,
+                                                   int n, int ns, const float* __restrict__ in0,
+                                                   const float* __restrict__ in1, const float* __restrict__ in2,
+                                                   int mean, double* __restrict__ out) {
+  __shared__ double red[4][256];
+  const int s = blockIdx.x, t = threadIdx.x;
+  const size_t plane = (size_t)ns * n, base = (size_t)s * n;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, c = 0.0;
+  for (int j = t; j < n; j += 256) {
+    a0 += partial[base + j];
+    a1 += partial[plane + base + j];
+    a2 += partial[2 * plane + base + j];
+    c += (double)pcount[base + j];
   }
-  out[s] = a0;
-  out[ns + s] = a1;
-  out[2 * ns + s] = a2;
-  out[3 * ns + s] = (double)c;
+  red[0][t] = a0;
+  red[1][t] = a1;
+  red[2][t] = a2;
+  red[3][t] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double v0 = red[0][0], v1 = red[1][0], v2 = red[2][0];
+    const double cnt = red[3][0];
+    if (mean) {
+      v0 = in0 ? v0 / ((double)in0[0] * cnt) : 0.0;
+      v1 = in1 ? v1 / ((double)in1[0] * cnt) : 0.0;
+      v2 = in2 ? v2 / ((double)in2[0] * cnt) : 0.0;
+    }
+    out[s] = v0;
+    out[ns + s] = v1;
+    out[2 * ns + s] = v2;
+    out[3 * ns + s] = cnt;
+  }
 }
 
 // W(s) = k_s^2 E(s) and L from E = out[0..ns), S = out[ns..2ns); writes W into
-// out[2ns..3ns) and L into out[4ns].
-__global__ void k_finish_spectra(double* __restrict__ out, int n, int ns) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double two_pi_n = 2.0 * 3.14159265358979323846 / (double)n;
+// out[2ns..3ns) and L into out[4ns].  One block, fixed tree.
+__global__ void __launch_bounds__(256) k_finish_spectra(double* __restrict__ out, int n, int ns) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x;
+  const double two_pi = 2.0 * 3.14159265358979323846, two_pi_n = two_pi / (double)n;
   double num = 0.0, den = 0.0;
-  for (int s = 0; s < ns; ++s) {
+  for (int s = t; s < ns; s += 256) {
     const double k = two_pi_n * s;
     out[2 * ns + s] = k * k * out[s];
     if (s > 0) {
@@ -185,7 +218,34 @@ __global__ void k_finish_spectra(double* __restrict__ out, int n, int ns) {
       den += k * out[ns + s];
     }
   }
-  out[4 * ns] = 2.0 * 3.14159265358979323846 * num / den;
+  red[0][t] = num;
+  red[1][t] = den;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] += red[0][t + w];
+      red[1][t] += red[1][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[4 * ns] = two_pi * red[0][0] / red[1][0];
+}
+
+// out[k] = scale * sum over blocks b of partial[b * cols + k]: one block per
+// column, fixed strided assignment and fixed tree.
+__global__ void __launch_bounds__(256) k_column_sum(const double* __restrict__ partial, int nblk, int cols,
+                                                    double scale, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double a = 0.0;
+  for (int b = t; b < nblk; b += 256) a += partial[(size_t)b * cols + k];
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[k] = red[0] * scale;
 }
 
 constexpr int kRedThreads = 256;
@@ -221,14 +281,6 @@ __global__ void __launch_bounds__(kRedThreads) k_overlaps(const float* __restric
   }
 }
 
-__global__ void k_overlaps_final(const double* __restrict__ partial, int nblk, double inv_sites,
-                                 double* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= 6) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)b * 6 + k];
-  out[k] = s * inv_sites;
-}
 
 // +-1/2 defects by winding number around every plaquette (float32 decisions).
 __device__ __forceinline__ float wrap_half(float d) {
@@ -238,7 +290,7 @@ __device__ __forceinline__ float wrap_half(float d) {
 }
 
 __global__ void __launch_bounds__(kRedThreads) k_defects(const float* __restrict__ s, int n,
-                                                         long long* __restrict__ partial) {
+                                                         double* __restrict__ partial) {
   __shared__ double red[kRedThreads / 64];
   const size_t n2 = (size_t)n * n;
   double plus = 0.0, minus = 0.0;  // integer counts carried exactly in doubles (< 2^53)
@@ -257,16 +309,9 @@ __global__ void __launch_bounds__(kRedThreads) k_defects(const float* __restrict
   const double p = block_sum(plus, red);
   const double m = block_sum(minus, red);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = (long long)p;
-    partial[2 * blockIdx.x + 1] = (long long)m;
+    partial[2 * blockIdx.x] = p;
+    partial[2 * blockIdx.x + 1] = m;
   }
-}
-
-__global__ void k_defects_final(const long long* __restrict__ partial, int nblk, long long* __restrict__ out) {
-  if (threadIdx.x > 1) return;
-  long long s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[2 * b + threadIdx.x];
-  out[threadIdx.x] = s;
 }
 
 }  // namespace
@@ -304,17 +349,16 @@ hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, in
 
 hipError_t launch_shells(const float* in0, const float* in1, const float* in2, int stride, int n, int ns, bool mean,
                          double* partial, int* pcount, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_shell_rows, dim3((n + 63) / 64), dim3(64), 0, st, in0, in1, in2, stride, n, ns, partial,
+  hipLaunchKernelGGL(k_shell_part, dim3((n + 255) / 256, ns), dim3(256), 0, st, in0, in1, in2, stride, n, ns, partial,
                      pcount);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_shell_reduce, dim3((ns + 63) / 64), dim3(64), 0, st, partial, pcount, n, ns, in0, in1, in2,
-                     mean ? 1 : 0, out);
+  hipLaunchKernelGGL(k_shell_sum, dim3(ns), dim3(256), 0, st, partial, pcount, n, ns, in0, in1, in2, mean ? 1 : 0, out);
   return hipGetLastError();
 }
 
 hipError_t launch_finish_spectra(double* out, int n, int ns, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_spectra, dim3(1), dim3(64), 0, st, out, n, ns);
+  hipLaunchKernelGGL(k_finish_spectra, dim3(1), dim3(256), 0, st, out, n, ns);
   return hipGetLastError();
 }
 
@@ -328,16 +372,16 @@ hipError_t launch_overlaps(const float* s0, const float* s1, int n, double* part
   hipLaunchKernelGGL(k_overlaps, dim3(nblk), dim3(kRedThreads), 0, st, s0, s1, n, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_overlaps_final, dim3(1), dim3(64), 0, st, partial, nblk, 1.0 / ((double)n * n), out);
+  hipLaunchKernelGGL(k_column_sum, dim3(6), dim3(256), 0, st, partial, nblk, 6, 1.0 / ((double)n * n), out);
   return hipGetLastError();
 }
 
-hipError_t launch_defects(const float* s, int n, long long* partial, long long* out, hipStream_t st) {
+hipError_t launch_defects(const float* s, int n, double* partial, double* out, hipStream_t st) {
   const int nblk = reduce_blocks(n);
   hipLaunchKernelGGL(k_defects, dim3(nblk), dim3(kRedThreads), 0, st, s, n, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_defects_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(k_column_sum, dim3(2), dim3(256), 0, st, partial, nblk, 2, 1.0, out);
   return hipGetLastError();
 }
 

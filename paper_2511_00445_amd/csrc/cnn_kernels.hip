@@ -368,12 +368,21 @@ __global__ void __launch_bounds__(kCmpThreads) k_compare(const float* __restrict
         (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-__global__ void k_compare_final(const double* __restrict__ partial, int nblk, double* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= 2 * kChannels) return;
-  double s = 0.0;
-  for (int i = 0; i < nblk; ++i) s += partial[(size_t)i * 2 * kChannels + k];
-  out[k] = s;
+// out[k] = sum over blocks of partial[block][k]: one block per k, fixed strided
+// assignment and fixed tree.
+__global__ void __launch_bounds__(256) k_compare_final(const double* __restrict__ partial, int nblk,
+                                                       double* __restrict__ out) {
+  __shared__ double red[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double a = 0.0;
+  for (int i = t; i < nblk; i += 256) a += partial[(size_t)i * 2 * kChannels + k];
+  red[t] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[k] = red[0];
 }
 
 }  // namespace
@@ -477,7 +486,7 @@ hipError_t launch_compare(const float* a, const float* b, int64_t plane, int B, 
   hipLaunchKernelGGL(k_compare, dim3(nblk), dim3(kCmpThreads), 0, st, a, b, plane, B, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_compare_final, dim3(1), dim3(64), 0, st, partial, nblk, out);
+  hipLaunchKernelGGL(k_compare_final, dim3(2 * kChannels), dim3(256), 0, st, partial, nblk, out);
   return hipGetLastError();
 }
 

@@ -453,8 +453,11 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
   using F = Fused<TH, MS>;
   constexpr int AW = F::AW, AH = F::AH, BW = F::BW, BH = F::BH, NT = F::NT;
   constexpr int FF_HA = F::HA, FF_HB = F::HB;
-  __shared__ float sphi[AH * AW], smu[AH * AW], sucx[AH * AW], sucy[AH * AW];
-  __shared__ float sqx[BH * BW], sqy[BH * BW], suax[BH * BW], suay[BH * BW];
+  // pairs that are always read together live interleaved (one 8-byte LDS read)
+  __shared__ float sphi[AH * AW], smu[AH * AW];
+  __shared__ float2 suc[AH * AW];  // (u_c,x, u_c,y)
+  __shared__ float2 sq[BH * BW];   // (Qxx, Qxy)
+  __shared__ float2 sua[BH * BW];  // (u_a,x, u_a,y)
   __shared__ unsigned scol[AW], srow[AH];
   const int nx = P.nx, ny = P.ny, n = P.n;
   const int gx = (nx + FF_X - 1) / FF_X;
@@ -501,24 +504,22 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
       const int c = tid + k * NT;
       if (c < AW * AH) {
         sphi[c] = va[k][0];
-        sucx[c] = va[k][1];
-        sucy[c] = va[k][2];
+        suc[c] = make_float2(va[k][1], va[k][2]);
       }
     }
 #pragma unroll
     for (int k = 0; k < F::KB; ++k) {
       const int c = tid + k * NT;
       if (c < BW * BH) {
-        sqx[c] = vb[k][0];
-        sqy[c] = vb[k][1];
-        suax[c] = vb[k][2];
-        suay[c] = vb[k][3];
+        sq[c] = make_float2(vb[k][0], vb[k][1]);
+        sua[c] = make_float2(vb[k][2], vb[k][3]);
       }
     }
   }
   __syncthreads();
   const Plane ophi = plane(out.phi, n), oqx = plane(out.q, n), oqy = plane(out.q + n, n);
   float pn[F::KP], qn[F::KQ][2];
+  int pp[F::KP], pq[F::KQ];  // LDS offsets of this thread's points (reused by the write-back)
   for (int m = 1; m <= S; ++m) {
     const int r = 2 * (S - m), s = S - m;  // halos of the boxes updated in this sub-step
     // (1) mu on the phi box of halo r + 1
@@ -540,13 +541,11 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
       if (c < cq) {
         const int cy = box_row(c, invq), cx = c - cy * wq;
         const int p = (cy + oq) * BW + (cx + oq);
-        const float2 ue = make_float2(suax[p + 1], suay[p + 1]), uw = make_float2(suax[p - 1], suay[p - 1]);
-        const float2 un = make_float2(suax[p + BW], suay[p + BW]), us = make_float2(suax[p - BW], suay[p - BW]);
+        pq[k] = p;
+        const float2 ue = sua[p + 1], uw = sua[p - 1], un = sua[p + BW], us = sua[p - BW];
         const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (un.x - us.x);
         const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (un.y - us.y);
-        const float2 nq = be_update(make_float2(sqx[p], sqy[p]), make_float2(sqx[p + 1], sqy[p + 1]),
-                                    make_float2(sqx[p - 1], sqy[p - 1]), make_float2(sqx[p + BW], sqy[p + BW]),
-                                    make_float2(sqx[p - BW], sqy[p - BW]), make_float2(suax[p], suay[p]),
+        const float2 nq = be_update(sq[p], sq[p + 1], sq[p - 1], sq[p + BW], sq[p - BW], sua[p],
                                     wxx, wxy, wyx, wyy, P.h, P);
         qn[k][0] = nq.x;
         qn[k][1] = nq.y;
@@ -562,8 +561,9 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
       if (c < cp) {
         const int cy = box_row(c, invp), cx = c - cy * wp;
         const int p = (cy + op) * AW + (cx + op);
-        const float div = 0.5f * (sphi[p + 1] * sucx[p + 1] - sphi[p - 1] * sucx[p - 1]) +
-                          0.5f * (sphi[p + AW] * sucy[p + AW] - sphi[p - AW] * sucy[p - AW]);
+        pp[k] = p;
+        const float div = 0.5f * (sphi[p + 1] * suc[p + 1].x - sphi[p - 1] * suc[p - 1].x) +
+                          0.5f * (sphi[p + AW] * suc[p + AW].y - sphi[p - AW] * suc[p - AW].y);
         const float lapmu = (smu[p + 1] + smu[p - 1]) + (smu[p + AW] + smu[p - AW]) - 4.f * smu[p];
         pn[k] = sphi[p] + P.h * (P.M * lapmu - div);
       }
@@ -572,23 +572,11 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
     // (4) write back: into the frames, or the tile to the output after the last sub-step
     if (m < S) {
 #pragma unroll
-      for (int k = 0; k < F::KP; ++k) {
-        const int c = tid + k * NT;
-        if (c < cp) {
-          const int cy = box_row(c, invp), cx = c - cy * wp;
-          sphi[(cy + op) * AW + (cx + op)] = pn[k];
-        }
-      }
+      for (int k = 0; k < F::KP; ++k)
+        if (tid + k * NT < cp) sphi[pp[k]] = pn[k];
 #pragma unroll
-      for (int k = 0; k < F::KQ; ++k) {
-        const int c = tid + k * NT;
-        if (c < cq) {
-          const int cy = box_row(c, invq), cx = c - cy * wq;
-          const int p = (cy + oq) * BW + (cx + oq);
-          sqx[p] = qn[k][0];
-          sqy[p] = qn[k][1];
-        }
-      }
+      for (int k = 0; k < F::KQ; ++k)
+        if (tid + k * NT < cq) sq[pq[k]] = make_float2(qn[k][0], qn[k][1]);
       __syncthreads();
     } else {
       // r = s = 0: both boxes are the tile, entry c = cy * 64 + cx

@@ -120,3 +120,13 @@ def test_temporal_overlaps():
     y[1:3] *= -1
     o = A.temporal_overlaps(x, y)
     assert abs(o[0] + o[1]) < 1e-12 and abs(o[2] + o[3]) < 1e-12 and abs(o[4] + o[5]) < 1e-12
+
+
+def test_overlap_norms_closed_form():
+    """Uniform fields: <|u_c|^2> = |u|^2, <Q:Q> = 2 S^2 for Q = S (cos 2t, sin 2t),
+    and the vorticity of a uniform flow is zero."""
+    N, S, t = 8, 0.3, 0.4
+    u = np.stack([np.full((N, N), 0.02), np.full((N, N), -0.01)])
+    x = state(N, qxx=np.full((N, N), S * np.cos(2 * t)), qxy=np.full((N, N), S * np.sin(2 * t)), ua=u)
+    o = A.temporal_overlaps(x, x)
+    assert abs(o[1] - (0.02 ** 2 + 0.01 ** 2)) < 1e-15 and abs(o[5] - 2 * S * S) < 1e-15 and o[3] == 0.0

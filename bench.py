@@ -335,7 +335,10 @@ def main():
     # per-launch HIP events on the first `sampled` timed steps only: an event pair
     # around every launch of all 2000 steps costs ~5% of the throughput
     fd = tuning[1]
-    block = {162: 2, 163: 3}.get(fd, p["n_sub"] if fd in (16, 32) and p["n_sub"] <= 5 else 1)
+    if fd == 165:
+        block = min(p["n_sub"], 5)
+    else:
+        block = {162: 2, 163: 3}.get(fd, p["n_sub"] if fd in (16, 32) and p["n_sub"] <= 5 else 1)
     launches_per_step = 1 + -(-p["n_sub"] // block)
     sampled = min(args.steps, 200)
     sim.kernel_timing(sampled * launches_per_step)

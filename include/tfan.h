@@ -175,8 +175,10 @@ const char* tfan_kernel_name(int id);
  * launches: 1, 2, 4: one launch per sub-step with that many rows per thread;
  * 16, 32: all n_sub sub-steps of a step in one launch on 64 x fd_shape tiles
  * (temporal blocking; for n_sub > 5 the 4-row per-sub-step launch runs);
- * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles.
- * Default (2, 16).  Results are bitwise identical for every shape; only the speed
+ * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
+ * 165: blocks of up to 5 sub-steps per launch on 64 x 32 tiles, the phi
+ * (Cahn-Hilliard) and Q (Beris-Edwards) sub-steps in separate thread blocks.
+ * Default (2, 165).  Results are bitwise identical for every shape; only the speed
  * differs.  Other values: TFAN_EINVAL. */
 int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape);
 int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_shape);

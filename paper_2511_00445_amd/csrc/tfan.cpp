@@ -193,14 +193,14 @@ int download(tfan_sim* s, double* dst, const float* src, size_t count, std::vect
 
 }  // namespace
 
-static const int kFdShapes[] = {1, 2, 4, 16, 32, 162, 163};
+static const int kFdShapes[] = {1, 2, 4, 16, 32, 162, 163, 165};
 static bool valid_shape(int32_t collide_rows, int32_t fd_shape) {
   if (collide_rows != 1 && collide_rows != 2) return false;
   for (int f : kFdShapes)
     if (f == fd_shape) return true;
   return false;
 }
-static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16, 32, 162 or 163";
+static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16, 32, 162, 163 or 165";
 // Shapes the autotuners try: every collide_rows with every fd_shape, skipping
 // blocked shapes that n_sub turns into the per-sub-step launch.
 static std::vector<tfan::Tuning> tuning_candidates(int n_sub) {

@@ -45,21 +45,26 @@ struct DevState {
 // launch per finite-difference sub-step with that many rows per thread;
 // {16, 32}: all sub-steps of a step in one launch on 64 x fd_shape tiles (n_sub
 // <= kFusedMaxSub, else one launch per sub-step with 4 rows per thread);
-// {162, 163}: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles.
-constexpr int kFusedMaxSub = 5;
+// {162, 163}: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
+// 165: blocks of up to kFusedMaxSub sub-steps on 64 x kSplitTile tiles, with
+// separate thread blocks for phi and Q in one launch.
+constexpr int kFusedMaxSub = 5, kSplitTile = 32;
 struct Tuning {
   int collide_rows = 2;
-  int fd_shape = 16;
+  int fd_shape = 165;
 };
 // Sub-steps per finite-difference launch (1: the per-sub-step kernel).
 inline int fd_block(const Tuning& tn, int n_sub) {
   if (tn.fd_shape == 162) return n_sub >= 2 ? 2 : 1;
   if (tn.fd_shape == 163) return n_sub >= 3 ? 3 : (n_sub == 2 ? 2 : 1);
   if (tn.fd_shape == 16 || tn.fd_shape == 32) return (n_sub >= 2 && n_sub <= kFusedMaxSub) ? n_sub : 1;
+  if (tn.fd_shape == 165) return n_sub >= 2 ? (n_sub < kFusedMaxSub ? n_sub : kFusedMaxSub) : 1;
   return 1;
 }
 // Tile rows of the blocked sub-step kernel.
 inline int fd_tile_rows(const Tuning& tn) { return tn.fd_shape == 32 ? 32 : 16; }
+// phi and Q advanced by separate thread blocks.
+inline bool fd_split(const Tuning& tn) { return tn.fd_shape == 165; }
 
 // One member of a batch of independent simulations (device-resident table).
 struct BatchMember {

@@ -437,6 +437,8 @@ template <int TH, int MS> struct Fused {
   // largest boxes updated into registers: phi with halo 2 MS - 2, Q with MS - 1
   static constexpr int KP = ((FF_X + 4 * MS - 4) * (TH + 4 * MS - 4) + NT - 1) / NT;
   static constexpr int KQ = ((FF_X + 2 * MS - 2) * (TH + 2 * MS - 2) + NT - 1) / NT;
+  // largest mu box: halo 2 MS - 1
+  static constexpr int KM = ((FF_X + 4 * MS - 2) * (TH + 4 * MS - 2) + NT - 1) / NT;
 };
 template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
   return ((nx + FF_X - 1) / FF_X) * ((ny + TH - 1) / TH);
@@ -445,6 +447,14 @@ template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
 // Row and column of entry c of a box w entries wide (c < 2^13, w >= 64): the
 // rounded product is at least 0.5 / w away from an integer, far above its error.
 __device__ __forceinline__ int box_row(int c, float inv_w) { return (int)(((float)c + 0.5f) * inv_w); }
+
+// Frame offset of entry c (row cy) of a box whose rows are `gap` entries
+// narrower than the frame and whose first entry sits at frame offset `base`:
+// (cy + o) * FW + (c - cy * w + o) = c + cy * (FW - w) + o * (FW + 1).  All
+// factors are below 2^13, so a 24-bit product is exact.
+__device__ __forceinline__ int frame_offset(int c, int cy, int gap, int base) {
+  return c + __mul24(cy, gap) + base;
+}
 
 // S (1 <= S <= MS) sub-steps from state `in` to state `out`.
 template <int TH, int MS>
@@ -518,29 +528,32 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
   }
   __syncthreads();
   const Plane ophi = plane(out.phi, n), oqx = plane(out.q, n), oqy = plane(out.q + n, n);
-  float pn[F::KP], qn[F::KQ][2];
-  int pp[F::KP], pq[F::KQ];  // LDS offsets of this thread's points (reused by the write-back)
+  constexpr int KP = F::KP, KQ = F::KQ, KM = F::KM;
+  float pn[KP], qn[KQ][2];
+  int pp[KP], pq[KQ];  // LDS offsets of this thread's points (reused by the write-back)
   for (int m = 1; m <= S; ++m) {
     const int r = 2 * (S - m), s = S - m;  // halos of the boxes updated in this sub-step
     // (1) mu on the phi box of halo r + 1
     {
       const int w = FF_X + 2 * (r + 1), cnt = w * (TH + 2 * (r + 1)), off = FF_HA - (r + 1);
       const float inv = 1.f / (float)w;
-      for (int c = tid; c < cnt; c += NT) {
-        const int cy = box_row(c, inv), cx = c - cy * w;
-        const int p = (cy + off) * AW + (cx + off);
-        smu[p] = chem_pot(sphi[p], sphi[p + 1], sphi[p - 1], sphi[p + AW], sphi[p - AW], P);
+#pragma unroll
+      for (int k = 0; k < KM; ++k) {
+        const int c = tid + k * NT;
+        if (c < cnt) {
+          const int p = frame_offset(c, box_row(c, inv), AW - w, off * (AW + 1));
+          smu[p] = chem_pot(sphi[p], sphi[p + 1], sphi[p - 1], sphi[p + AW], sphi[p - AW], P);
+        }
       }
     }
     // (2) Beris-Edwards update on the Q box of halo s, into registers
     const int wq = FF_X + 2 * s, cq = wq * (TH + 2 * s), oq = FF_HB - s;
     const float invq = 1.f / (float)wq;
 #pragma unroll
-    for (int k = 0; k < F::KQ; ++k) {
+    for (int k = 0; k < KQ; ++k) {
       const int c = tid + k * NT;
       if (c < cq) {
-        const int cy = box_row(c, invq), cx = c - cy * wq;
-        const int p = (cy + oq) * BW + (cx + oq);
+        const int p = frame_offset(c, box_row(c, invq), BW - wq, oq * (BW + 1));
         pq[k] = p;
         const float2 ue = sua[p + 1], uw = sua[p - 1], un = sua[p + BW], us = sua[p - BW];
         const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (un.x - us.x);
@@ -556,11 +569,10 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
     const int wp = FF_X + 2 * r, cp = wp * (TH + 2 * r), op = FF_HA - r;
     const float invp = 1.f / (float)wp;
 #pragma unroll
-    for (int k = 0; k < F::KP; ++k) {
+    for (int k = 0; k < KP; ++k) {
       const int c = tid + k * NT;
       if (c < cp) {
-        const int cy = box_row(c, invp), cx = c - cy * wp;
-        const int p = (cy + op) * AW + (cx + op);
+        const int p = frame_offset(c, box_row(c, invp), AW - wp, op * (AW + 1));
         pp[k] = p;
         const float div = 0.5f * (sphi[p + 1] * suc[p + 1].x - sphi[p - 1] * suc[p - 1].x) +
                           0.5f * (sphi[p + AW] * suc[p + AW].y - sphi[p - AW] * suc[p - AW].y);
@@ -568,20 +580,20 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
         pn[k] = sphi[p] + P.h * (P.M * lapmu - div);
       }
     }
-    __syncthreads();
+    __syncthreads();  // every read of this sub-step's frames done
     // (4) write back: into the frames, or the tile to the output after the last sub-step
     if (m < S) {
 #pragma unroll
-      for (int k = 0; k < F::KP; ++k)
+      for (int k = 0; k < KP; ++k)
         if (tid + k * NT < cp) sphi[pp[k]] = pn[k];
 #pragma unroll
-      for (int k = 0; k < F::KQ; ++k)
+      for (int k = 0; k < KQ; ++k)
         if (tid + k * NT < cq) sq[pq[k]] = make_float2(qn[k][0], qn[k][1]);
       __syncthreads();
     } else {
       // r = s = 0: both boxes are the tile, entry c = cy * 64 + cx
 #pragma unroll
-      for (int k = 0; k < F::KQ; ++k) {
+      for (int k = 0; k < KQ; ++k) {
         const int c = tid + k * NT;
         const int cy = c / FF_X, cx = c - cy * FF_X;
         if (c < FF_X * TH && x0 + cx < nx && y0 + cy < ny) {
@@ -591,7 +603,7 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
         }
       }
 #pragma unroll
-      for (int k = 0; k < F::KP; ++k) {
+      for (int k = 0; k < KP; ++k) {
         const int c = tid + k * NT;
         const int cy = c / FF_X, cx = c - cy * FF_X;
         if (c < FF_X * TH && x0 + cx < nx && y0 + cy < ny)
@@ -618,6 +630,325 @@ __global__ void __launch_bounds__((Fused<TH, MS>::NT)) k_fd_fused_batch(const Ba
   const int m = batch_member(first, count, tile);
   const DevParams P = mem[m].P;
   fd_fused_tile<TH, MS>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m], subs);
+}
+
+// ---------------------------------------------------------------------------
+// The same temporal blocking with the two fields in separate thread blocks (the
+// sub-steps of phi and Q are independent with u_a and u_c frozen), so that each
+// block holds only its own frames in LDS.  Threads update strips of R vertically
+// consecutive sites of one column: the north/south stencil values of a strip are
+// read once from LDS and shared through registers.  Site arithmetic is that of
+// fd_tile, term for term.  On 64 x 32 tiles with five sub-steps the phi block
+// recomputes 1.5x (mu) and 1.4x (phi) the sites of its tile, the Q block 1.2x.
+// ---------------------------------------------------------------------------
+template <int TH, int MS> struct PhiBlock {
+  static constexpr int H = 2 * MS;                           // frame halo
+  static constexpr int W = FF_X + 2 * H, HT = TH + 2 * H;    // frame width, height
+  static constexpr int NT = 1024;
+  static constexpr int RM = 2, RP = 4;                       // strip heights: mu, phi
+  static constexpr int KS = (W * HT + NT - 1) / NT;
+  // largest boxes: mu with halo 2 MS - 1, phi with halo 2 MS - 2
+  static constexpr int KM = ((FF_X + 4 * MS - 2) * ((TH + 4 * MS - 2) / RM) + NT - 1) / NT;
+  static constexpr int KP = ((FF_X + 4 * MS - 4) * ((TH + 4 * MS - 4) / RP) + NT - 1) / NT;
+  static constexpr int LDS = 4 * HT * W * 4 + (W + HT) * 4;  // phi, mu, u_c,x, u_c,y, sources
+  static_assert(TH % RP == 0, "box heights must be whole strips");
+};
+template <int TH, int MS> struct QBlock {
+  static constexpr int H = MS;
+  static constexpr int W = FF_X + 2 * H, HT = TH + 2 * H;
+  static constexpr int NT = 1024;
+  static constexpr int R = 2;
+  static constexpr int KS = (W * HT + NT - 1) / NT;
+  static constexpr int KQ = ((FF_X + 2 * MS - 2) * ((TH + 2 * MS - 2) / R) + NT - 1) / NT;
+  static constexpr int LDS = 2 * HT * W * 8 + (W + HT) * 4;  // Q, u_a, sources
+  static_assert(TH % R == 0, "box heights must be whole strips");
+};
+
+// Periodic source offsets of the columns and rows of a frame with halo h.
+__device__ __forceinline__ void frame_sources(unsigned* scol, unsigned* srow, int w, int ht, int x0, int y0,
+                                              int h, int nx, int ny, int nt) {
+  for (int i = threadIdx.x; i < w + ht; i += nt) {
+    if (i < w) {
+      const int g = (x0 - h + i) % nx;
+      scol[i] = (unsigned)(g < 0 ? g + nx : g);
+    } else {
+      const int g = (y0 - h + (i - w)) % ny;
+      srow[i - w] = (unsigned)(g < 0 ? g + ny : g) * (unsigned)nx;
+    }
+  }
+}
+
+// S (1 <= S <= MS) Cahn-Hilliard sub-steps of phi from `in` to `out`.
+template <int TH, int MS>
+__device__ __forceinline__ void phi_block_tile(const DevParams& P, const DevState& in, const DevState& out,
+                                               const float* __restrict__ U, int tile, int S,
+                                               unsigned char* __restrict__ lds) {
+  using B = PhiBlock<TH, MS>;
+  constexpr int W = B::W, HT = B::HT, NT = B::NT, H = B::H;
+  float* sphi = reinterpret_cast<float*>(lds);
+  float* smu = sphi + HT * W;
+  float* sux = smu + HT * W;
+  float* suy = sux + HT * W;
+  unsigned* scol = reinterpret_cast<unsigned*>(suy + HT * W);
+  unsigned* srow = scol + W;
+  const int nx = P.nx, ny = P.ny, n = P.n;
+  const int gx = (nx + FF_X - 1) / FF_X;
+  const int x0 = (tile % gx) * FF_X, y0 = (tile / gx) * TH;
+  const int tid = threadIdx.x;
+  frame_sources(scol, srow, W, HT, x0, y0, H, nx, ny, NT);
+  __syncthreads();
+  {
+    const Plane ph = plane(in.phi, n), ucx = plane(U + 2 * n, n), ucy = plane(U + 3 * n, n);
+    float v[B::KS][3];
+#pragma unroll
+    for (int k = 0; k < B::KS; ++k) {
+      const int c = min(tid + k * NT, W * HT - 1);
+      const int cy = c / W, cx = c - cy * W;
+      const unsigned g = srow[cy] + scol[cx];
+      v[k][0] = ldg(ph, g);
+      v[k][1] = ldg(ucx, g);
+      v[k][2] = ldg(ucy, g);
+    }
+#pragma unroll
+    for (int k = 0; k < B::KS; ++k) {
+      const int c = tid + k * NT;
+      if (c < W * HT) {
+        sphi[c] = v[k][0];
+        sux[c] = v[k][1];
+        suy[c] = v[k][2];
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int RP = B::RP;
+  float pn[B::KP][RP];
+  int pp[B::KP];
+  for (int m = 1; m <= S; ++m) {
+    const int r = 2 * (S - m);  // halo of the phi box of this sub-step
+    // (1) mu on the box of halo r + 1, two rows per strip
+    {
+      const int w = FF_X + 2 * (r + 1), cnt = w * ((TH + 2 * (r + 1)) / 2), o = H - (r + 1);
+      const float inv = 1.f / (float)w;
+#pragma unroll
+      for (int k = 0; k < B::KM; ++k) {
+        const int c = tid + k * NT;
+        if (c < cnt) {
+          const int p = frame_offset(c, box_row(c, inv), 2 * W - w, o * (W + 1));
+          const float a0 = sphi[p - W], a1 = sphi[p], a2 = sphi[p + W], a3 = sphi[p + 2 * W];
+          smu[p] = chem_pot(a1, sphi[p + 1], sphi[p - 1], a2, a0, P);
+          smu[p + W] = chem_pot(a2, sphi[p + W + 1], sphi[p + W - 1], a3, a1, P);
+        }
+      }
+    }
+    __syncthreads();
+    // (2) phi on the box of halo r, RP rows per strip, into registers
+    const int w = FF_X + 2 * r, cnt = w * ((TH + 2 * r) / RP), o = H - r;
+    const float inv = 1.f / (float)w;
+#pragma unroll
+    for (int k = 0; k < B::KP; ++k) {
+      const int c = tid + k * NT;
+      if (c < cnt) {
+        const int p = frame_offset(c, box_row(c, inv), RP * W - w, o * (W + 1));
+        pp[k] = p;
+        float ph[RP + 2], uy[RP + 2], mu[RP + 2];
+#pragma unroll
+        for (int j = 0; j < RP + 2; ++j) {
+          const int q = p + (j - 1) * W;
+          ph[j] = sphi[q];
+          uy[j] = suy[q];
+          mu[j] = smu[q];
+        }
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          const int q = p + j * W;
+          const float div = 0.5f * (sphi[q + 1] * sux[q + 1] - sphi[q - 1] * sux[q - 1]) +
+                            0.5f * (ph[j + 2] * uy[j + 2] - ph[j] * uy[j]);
+          const float lapmu = (smu[q + 1] + smu[q - 1]) + (mu[j + 2] + mu[j]) - 4.f * mu[j + 1];
+          pn[k][j] = ph[j + 1] + P.h * (P.M * lapmu - div);
+        }
+      }
+    }
+    __syncthreads();
+    // (3) write back into the frame, or the tile to the output after the last sub-step
+    if (m < S) {
+#pragma unroll
+      for (int k = 0; k < B::KP; ++k)
+        if (tid + k * NT < cnt) {
+#pragma unroll
+          for (int j = 0; j < RP; ++j) sphi[pp[k] + j * W] = pn[k][j];
+        }
+      __syncthreads();
+    } else {
+      // r = 0: strip c covers rows RP * (c / 64) .. + RP - 1 of column c % 64
+      const Plane ophi = plane(out.phi, n);
+#pragma unroll
+      for (int k = 0; k < B::KP; ++k) {
+        const int c = tid + k * NT;
+        const int sy = c / FF_X, cx = c - sy * FF_X;
+        if (c < cnt && x0 + cx < nx) {
+#pragma unroll
+          for (int j = 0; j < RP; ++j) {
+            const int y = y0 + RP * sy + j;
+            if (y < ny) stg(ophi, (unsigned)y * (unsigned)nx + (unsigned)(x0 + cx), pn[k][j]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// S (1 <= S <= MS) Beris-Edwards sub-steps of Q from `in` to `out`.
+template <int TH, int MS>
+__device__ __forceinline__ void q_block_tile(const DevParams& P, const DevState& in, const DevState& out,
+                                             const float* __restrict__ U, int tile, int S,
+                                             unsigned char* __restrict__ lds) {
+  using B = QBlock<TH, MS>;
+  constexpr int W = B::W, HT = B::HT, NT = B::NT, H = B::H, R = B::R;
+  float2* sq = reinterpret_cast<float2*>(lds);  // (Qxx, Qxy)
+  float2* sua = sq + HT * W;                    // (u_a,x, u_a,y)
+  unsigned* scol = reinterpret_cast<unsigned*>(sua + HT * W);
+  unsigned* srow = scol + W;
+  const int nx = P.nx, ny = P.ny, n = P.n;
+  const int gx = (nx + FF_X - 1) / FF_X;
+  const int x0 = (tile % gx) * FF_X, y0 = (tile / gx) * TH;
+  const int tid = threadIdx.x;
+  frame_sources(scol, srow, W, HT, x0, y0, H, nx, ny, NT);
+  __syncthreads();
+  {
+    const Plane qx = plane(in.q, n), qy = plane(in.q + n, n), uax = plane(U, n), uay = plane(U + n, n);
+    float v[B::KS][4];
+#pragma unroll
+    for (int k = 0; k < B::KS; ++k) {
+      const int c = min(tid + k * NT, W * HT - 1);
+      const int cy = c / W, cx = c - cy * W;
+      const unsigned g = srow[cy] + scol[cx];
+      v[k][0] = ldg(qx, g);
+      v[k][1] = ldg(qy, g);
+      v[k][2] = ldg(uax, g);
+      v[k][3] = ldg(uay, g);
+    }
+#pragma unroll
+    for (int k = 0; k < B::KS; ++k) {
+      const int c = tid + k * NT;
+      if (c < W * HT) {
+        sq[c] = make_float2(v[k][0], v[k][1]);
+        sua[c] = make_float2(v[k][2], v[k][3]);
+      }
+    }
+  }
+  __syncthreads();
+  float2 qn[B::KQ][R];
+  int pq[B::KQ];
+  for (int m = 1; m <= S; ++m) {
+    const int s = S - m;  // halo of the Q box of this sub-step
+    const int w = FF_X + 2 * s, cnt = w * ((TH + 2 * s) / R), o = H - s;
+    const float inv = 1.f / (float)w;
+#pragma unroll
+    for (int k = 0; k < B::KQ; ++k) {
+      const int c = tid + k * NT;
+      if (c < cnt) {
+        const int p = frame_offset(c, box_row(c, inv), R * W - w, o * (W + 1));
+        pq[k] = p;
+        float2 qc[R + 2], ac[R + 2];
+#pragma unroll
+        for (int j = 0; j < R + 2; ++j) {
+          qc[j] = sq[p + (j - 1) * W];
+          ac[j] = sua[p + (j - 1) * W];
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const int q = p + j * W;
+          const float2 ue = sua[q + 1], uw = sua[q - 1];
+          const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (ac[j + 2].x - ac[j].x);
+          const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (ac[j + 2].y - ac[j].y);
+          qn[k][j] = be_update(qc[j + 1], sq[q + 1], sq[q - 1], qc[j + 2], qc[j], ac[j + 1], wxx, wxy, wyx, wyy,
+                               P.h, P);
+        }
+      }
+    }
+    __syncthreads();
+    if (m < S) {
+#pragma unroll
+      for (int k = 0; k < B::KQ; ++k)
+        if (tid + k * NT < cnt) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) sq[pq[k] + j * W] = qn[k][j];
+        }
+      __syncthreads();
+    } else {
+      const Plane oqx = plane(out.q, n), oqy = plane(out.q + n, n);
+#pragma unroll
+      for (int k = 0; k < B::KQ; ++k) {
+        const int c = tid + k * NT;
+        const int sy = c / FF_X, cx = c - sy * FF_X;
+        if (c < cnt && x0 + cx < nx) {
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const int y = y0 + R * sy + j;
+            if (y < ny) {
+              const unsigned g = (unsigned)y * (unsigned)nx + (unsigned)(x0 + cx);
+              stg(oqx, g, qn[k][j].x);
+              stg(oqy, g, qn[k][j].y);
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// phi and Q tiles in one grid that shares one LDS allocation, so that the
+// LDS-latency-bound phi blocks and the VALU-bound Q blocks run side by side on
+// the compute units.  Work item t of the XCD-ordered grid belongs to group
+// g = t / kPairGroup; even groups are phi tiles and odd groups Q tiles, the
+// group pair g / 2 covering tiles [(g / 2) kPairGroup, (g / 2 + 1) kPairGroup).
+// With kPairGroup = 64 (the block slots of one XCD) the blocks resident on a
+// compute unit are mostly one of each kind.
+constexpr int kPairGroup = 64;
+template <int TH, int MS> struct PairBlock {
+  static constexpr int NT = PhiBlock<TH, MS>::NT;
+  static constexpr int LDS = PhiBlock<TH, MS>::LDS > QBlock<TH, MS>::LDS ? PhiBlock<TH, MS>::LDS : QBlock<TH, MS>::LDS;
+  static_assert(PhiBlock<TH, MS>::NT == QBlock<TH, MS>::NT, "one block size for both fields");
+};
+__host__ __device__ inline int pair_items(int tiles) {
+  return 2 * ((tiles + kPairGroup - 1) / kPairGroup) * kPairGroup;
+}
+// Tile of work item t and whether it advances phi (else Q); -1 for a spare item.
+__device__ __forceinline__ int pair_tile(int t, int tiles, bool& phi) {
+  const int g = t / kPairGroup;
+  const int tile = (g >> 1) * kPairGroup + (t - g * kPairGroup);
+  phi = (g & 1) == 0;
+  return tile < tiles ? tile : -1;
+}
+
+template <int TH, int MS>
+__global__ void __launch_bounds__((PairBlock<TH, MS>::NT), 8) k_fd_pair(DevParams P, DevState in, DevState out,
+                                                                      const float* __restrict__ U, int subs) {
+  __shared__ __align__(16) unsigned char lds[PairBlock<TH, MS>::LDS];
+  const int tiles = fused_tiles<TH>(P.nx, P.ny);
+  const int t = xcd_tile(pair_items(tiles));
+  if (t < 0) return;
+  bool phi;
+  const int tile = pair_tile(t, tiles, phi);
+  if (tile < 0) return;
+  if (phi) phi_block_tile<TH, MS>(P, in, out, U, tile, subs, lds);
+  else q_block_tile<TH, MS>(P, in, out, U, tile, subs, lds);
+}
+
+template <int TH, int MS>
+__global__ void __launch_bounds__((PairBlock<TH, MS>::NT), 8) k_fd_pair_batch(const BatchMember* __restrict__ mem,
+                                                                            const int* __restrict__ first, int count,
+                                                                            int tiles, int src, int subs) {
+  __shared__ __align__(16) unsigned char lds[PairBlock<TH, MS>::LDS];
+  const int t = xcd_tile(pair_items(tiles));
+  if (t < 0) return;
+  bool phi;
+  const int tile = pair_tile(t, tiles, phi);
+  if (tile < 0) return;
+  const int m = batch_member(first, count, tile);
+  const DevParams P = mem[m].P;
+  if (phi) phi_block_tile<TH, MS>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m], subs, lds);
+  else q_block_tile<TH, MS>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m], subs, lds);
 }
 
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
@@ -798,6 +1129,12 @@ hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, int subs,
                      hipStream_t st) {
   const int block = fd_block(tn, P.n_sub);
+  if (block > 1 && fd_split(tn)) {
+    const dim3 grid(xcd_grid(pair_items(fused_tiles<kSplitTile>(P.nx, P.ny))));
+    hipLaunchKernelGGL((k_fd_pair<kSplitTile, kFusedMaxSub>), grid, dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), 0,
+                       st, P, in, out, u, subs);
+    return hipGetLastError();
+  }
   if (block > 1) {
     const int th = fd_tile_rows(tn);
 #define TFAN_FUSED(TH_, MS_)                                                                                  \
@@ -820,7 +1157,10 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
 
 int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
   if (collide) return tn.collide_rows == 1 ? collide_tiles<1>(P.nx, P.ny) : collide_tiles<2>(P.nx, P.ny);
-  if (fd_block(tn, P.n_sub) > 1) return fd_tile_rows(tn) == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
+  if (fd_block(tn, P.n_sub) > 1) {
+    if (fd_split(tn)) return fused_tiles<kSplitTile>(P.nx, P.ny);
+    return fd_tile_rows(tn) == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
+  }
   return tn.fd_shape == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_shape == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
 }
 
@@ -841,6 +1181,11 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
                            int n_sub, int subs, hipStream_t st) {
   const dim3 grid(xcd_grid(tiles)), blk(FD_TX, FD_TY);
   const int block = fd_block(tn, n_sub);
+  if (block > 1 && fd_split(tn)) {
+    hipLaunchKernelGGL((k_fd_pair_batch<kSplitTile, kFusedMaxSub>), dim3(xcd_grid(pair_items(tiles))),
+                       dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), 0, st, mem, first, count, tiles, src, subs);
+    return hipGetLastError();
+  }
   if (block > 1) {
 #define TFAN_FUSED_B(TH_, MS_) \
   hipLaunchKernelGGL((k_fd_fused_batch<TH_, MS_>), grid, dim3(Fused<TH_, MS_>::NT), 0, st, mem, first, count, tiles, src, subs)

@@ -9,8 +9,8 @@ from paper_2511_00445_amd.workloads import base_params, initial_fields
 
 pytestmark = pytest.mark.gpu
 # fd_shape 1, 2, 4: one launch per sub-step; 16, 32: all sub-steps in one launch;
-# 162, 163: blocks of 2 or 3 sub-steps per launch
-SHAPES = [(c, f) for c in (1, 2) for f in (1, 2, 4, 16, 32, 162, 163)]
+# 162, 163: blocks of 2 or 3 sub-steps per launch; 165: phi and Q in separate launches
+SHAPES = [(c, f) for c in (1, 2) for f in (1, 2, 4, 16, 32, 162, 163, 165)]
 
 
 def say(msg):
@@ -49,7 +49,7 @@ def test_fused_substeps_match_per_substep_launches(gpu, n_sub, nx, ny):
     p = base_params(nx, ny, zeta=0.03, lam=1.2, n_sub=n_sub)
     ic = initial_fields(nx, ny, seed=30 + n_sub, phi_noise=0.5, S0=0.3)
     ref = single(p, ic, 12, (2, 4)).get_state()
-    for f in (16, 32, 162, 163):
+    for f in (16, 32, 162, 163, 165):
         assert np.array_equal(single(p, ic, 12, (2, f)).get_state(), ref), f
 
 
@@ -73,7 +73,7 @@ def _members():
             dict(p=base_params(128, 128, tau_a=0.8, tau_p=1.3), ic=initial_fields(128, 128, seed=4, phi_mean=-0.3))]
 
 
-@pytest.mark.parametrize("shape", [(2, 4), (1, 1), (2, 32), (1, 16), (2, 162), (1, 163)])
+@pytest.mark.parametrize("shape", [(2, 4), (1, 1), (2, 32), (1, 16), (2, 162), (1, 163), (2, 165)])
 def test_batch_members_match_single_runs(gpu, shape):
     from paper_2511_00445_amd import Batch
     say(f"case: batch vs single, shape {shape}")

@@ -282,7 +282,7 @@ def main():
                     help="population storage (f16: binary16 deviations, float32 arithmetic)")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--train-steps", type=int, default=6000,
+    ap.add_argument("--train-steps", type=int, default=12000,
                     help="surrogate_1024: Adam steps of the surrogate's training")
     ap.add_argument("--tuning", default="", metavar="C,F",
                     help="launch shape collide_rows,fd_shape (default: the library's)")

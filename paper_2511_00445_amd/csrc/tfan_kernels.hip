@@ -145,23 +145,29 @@ __device__ __forceinline__ void stg(Plane r, unsigned idx, float v) {
 }
 
 // One forward-Euler Beris-Edwards update of (Qxx, Qxy) (Model, Eqs. 11-12) at a
-// site: Q += h Proj[ -u_a.grad Q + S(W, Q) + Gamma H ], with W_ij = d_j u_a,i given.
-// The symmetric traceless part of S(W, Q) in two dimensions is
-// lam E_dev + lam tr(W) Q - 2 lam (Q:E) Q + (Om.Q - Q.Om).
-__device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, float2 qn, float2 qs,
-                                            float2 u, float wxx, float wxy, float wyx, float wyy,
-                                            float h, const DevParams& P) {
-  const float d = 0.5f * (wxx - wyy), e = 0.5f * (wxy + wyx), tr = wxx + wyy;
-  const float om = 0.5f * (wxy - wyx);
-  const float b = P.A_ldg + P.halfC * (2.f * (q.x * q.x + q.y * q.y));
-  const float hxx = P.K * ((qe.x + qw.x) + (qn.x + qs.x) - 4.f * q.x) - b * q.x;
-  const float hxy = P.K * ((qe.y + qw.y) + (qn.y + qs.y) - 4.f * q.y) - b * q.y;
-  const float g = P.lam * (tr - 4.f * (q.x * d + q.y * e));
-  const float sxx = P.lam * d + g * q.x + 2.f * om * q.y;
-  const float sxy = P.lam * e + g * q.y - 2.f * om * q.x;
-  const float advx = -(u.x * 0.5f * (qe.x - qw.x) + u.y * 0.5f * (qn.x - qs.x));
-  const float advy = -(u.x * 0.5f * (qe.y - qw.y) + u.y * 0.5f * (qn.y - qs.y));
-  return make_float2(q.x + h * (advx + sxx + P.Gamma * hxx), q.y + h * (advy + sxy + P.Gamma * hxy));
+// site: Q += h Proj[ -u_a.grad Q + S(W, Q) + Gamma H ], W_ij = d_j u_a,i by central
+// differences of the four neighbouring velocities.  The symmetric traceless part
+// of S(W, Q) in two dimensions is lam E_dev + lam tr(W) Q - 2 lam (Q:E) Q +
+// (Om.Q - Q.Om).  With g_ij = 2 W_ij (the undivided differences):
+// 4 E_dev = (g_xx - g_yy, g_xy + g_yx), 2 tr W = g_xx + g_yy, 4 Om_xy = g_xy - g_yx,
+// and S_xx = lam E_xx + G Q_xx + 2 Om_xy Q_xy, S_xy = lam E_xy + G Q_xy - 2 Om_xy Q_xx
+// with G = lam (tr W - 2 Q:E) (Q:E = 2 (Q_xx E_xx + Q_xy E_xy)).
+__device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, float2 qn, float2 qs, float2 u,
+                                            float2 ue, float2 uw, float2 un, float2 us, float h,
+                                            const DevParams& P) {
+  const float gxx = ue.x - uw.x, gxy = un.x - us.x, gyx = ue.y - uw.y, gyy = un.y - us.y;
+  const float exx4 = gxx - gyy, exy4 = gxy + gyx, tr2 = gxx + gyy, om2 = 0.5f * (gxy - gyx);
+  const float b = P.A_ldg + (2.f * P.halfC) * (q.x * q.x + q.y * q.y);
+  const float hxx = P.K * (((qe.x + qw.x) + (qn.x + qs.x)) - 4.f * q.x) - b * q.x;
+  const float hxy = P.K * (((qe.y + qw.y) + (qn.y + qs.y)) - 4.f * q.y) - b * q.y;
+  const float g = P.lam * (0.5f * tr2 - (q.x * exx4 + q.y * exy4));
+  const float lq = 0.25f * P.lam;
+  const float sxx = lq * exx4 + g * q.x + om2 * q.y;
+  const float sxy = lq * exy4 + g * q.y - om2 * q.x;
+  // twice the advection u_a . grad Q
+  const float ax = u.x * (qe.x - qw.x) + u.y * (qn.x - qs.x);
+  const float ay = u.x * (qe.y - qw.y) + u.y * (qn.y - qs.y);
+  return make_float2(q.x + h * ((sxx + P.Gamma * hxx) - 0.5f * ax), q.y + h * ((sxy + P.Gamma * hxy) - 0.5f * ay));
 }
 
 // Tiles of the collision kernel: CT_X x (4 * SITES) sites, SITES rows per thread.
@@ -386,9 +392,7 @@ __device__ __forceinline__ void fd_tile(const DevParams& P, const DevState& in, 
     const unsigned oe = row[j + 2] + xp1, ow = row[j + 2] + xm1;
     const float2 qe = make_float2(ldg(qx, oe), ldg(qy, oe)), qw = make_float2(ldg(qx, ow), ldg(qy, ow));
     const float2 ue = make_float2(ldg(ax, oe), ldg(ay, oe)), uw = make_float2(ldg(ax, ow), ldg(ay, ow));
-    const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (ac[j + 2].x - ac[j].x);
-    const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (ac[j + 2].y - ac[j].y);
-    const float2 nq = be_update(qc[j + 1], qe, qw, qc[j + 2], qc[j], ac[j + 1], wxx, wxy, wyx, wyy, P.h, P);
+    const float2 nq = be_update(qc[j + 1], qe, qw, qc[j + 2], qc[j], ac[j + 1], ue, uw, ac[j + 2], ac[j], P.h, P);
     const unsigned o = row[j + 2] + xc;
     stg(oqx, o, nq.x);
     stg(oqy, o, nq.y);
@@ -555,11 +559,8 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
       if (c < cq) {
         const int p = frame_offset(c, box_row(c, invq), BW - wq, oq * (BW + 1));
         pq[k] = p;
-        const float2 ue = sua[p + 1], uw = sua[p - 1], un = sua[p + BW], us = sua[p - BW];
-        const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (un.x - us.x);
-        const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (un.y - us.y);
-        const float2 nq = be_update(sq[p], sq[p + 1], sq[p - 1], sq[p + BW], sq[p - BW], sua[p],
-                                    wxx, wxy, wyx, wyy, P.h, P);
+        const float2 nq = be_update(sq[p], sq[p + 1], sq[p - 1], sq[p + BW], sq[p - BW], sua[p], sua[p + 1],
+                                    sua[p - 1], sua[p + BW], sua[p - BW], P.h, P);
         qn[k][0] = nq.x;
         qn[k][1] = nq.y;
       }
@@ -858,11 +859,8 @@ __device__ __forceinline__ void q_block_tile(const DevParams& P, const DevState&
 #pragma unroll
         for (int j = 0; j < R; ++j) {
           const int q = p + j * W;
-          const float2 ue = sua[q + 1], uw = sua[q - 1];
-          const float wxx = 0.5f * (ue.x - uw.x), wxy = 0.5f * (ac[j + 2].x - ac[j].x);
-          const float wyx = 0.5f * (ue.y - uw.y), wyy = 0.5f * (ac[j + 2].y - ac[j].y);
-          qn[k][j] = be_update(qc[j + 1], sq[q + 1], sq[q - 1], qc[j + 2], qc[j], ac[j + 1], wxx, wxy, wyx, wyy,
-                               P.h, P);
+          qn[k][j] = be_update(qc[j + 1], sq[q + 1], sq[q - 1], qc[j + 2], qc[j], ac[j + 1], sua[q + 1], sua[q - 1],
+                               ac[j + 2], ac[j], P.h, P);
         }
       }
     }

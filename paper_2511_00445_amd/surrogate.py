@@ -29,7 +29,8 @@ from .binding import Cnn, Sim
 from .workloads import initial_fields
 
 K_STEPS = 50
-RELAX_STEPS = 25   # solver steps after each jump in the deploy loop
+RELAX_STEPS = 25     # solver steps after each jump in the deploy loop
+TRAIN_STEPS = 12000  # Adam steps of the standard training run (batches of 8)
 
 
 def trajectory_pairs(params: dict, seeds, t0: int, t1: int, k: int = K_STEPS, phi_mean: float = 0.0):

@@ -275,8 +275,10 @@ class Sim:
         self._check(self.lib.tfan_kernel_timing(self._handle, int(cap)))
 
     def set_tuning(self, collide_rows: int, fd_shape: int):
-        """collide_rows in {1, 2}; fd_shape in {1, 2, 4} (one launch per sub-step) or
-        {16, 32} (all sub-steps of a step in one launch, n_sub <= 5)."""
+        """Launch shape (results are bitwise the same for every shape): collide_rows in
+        {1, 2} rows of sites per thread; fd_shape in {1, 2, 4} (one launch per sub-step), {16, 32, 162, 163}
+        (blocked sub-steps, both fields per block) or 165 (blocked, phi and Q in separate
+        blocks).  tfan.h documents each shape."""
         self._check(self.lib.tfan_set_tuning(self._handle, int(collide_rows), int(fd_shape)))
 
     def get_tuning(self) -> tuple:

@@ -80,10 +80,9 @@ __device__ __forceinline__ Stress nematic_stress(float qxx, float qxy, float qxx
 // BGK collision with the Guo source for one fluid, written post-collision:
 // f* = f + (f^eq - f)/tau + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F,
 // all populations shifted by -w_i rho0.
-template <typename PT>
-__device__ __forceinline__ void collide_fluid(const float f[9], float dr, float ux, float uy,
-                                              float Fx, float Fy, float om, float gk, float rho0,
-                                              void* __restrict__ out, size_t base, int n, int idx) {
+// The populations f are replaced by their post-collision values.
+__device__ __forceinline__ void collide_fluid(float f[9], float dr, float ux, float uy, float Fx, float Fy,
+                                              float om, float gk, float rho0) {
   const float rho = rho0 + dr;
   const float uu15 = 1.5f * (ux * ux + uy * uy);
   const float uF = ux * Fx + uy * Fy;
@@ -93,7 +92,66 @@ __device__ __forceinline__ void collide_fluid(const float f[9], float dr, float 
     const float cF = (float)CX[i] * Fx + (float)CY[i] * Fy;
     const float feq = WT[i] * (dr + rho * (cu * (3.f + 4.5f * cu) - uu15));
     const float src = gk * WT[i] * (3.f * (cF - uF) + 9.f * cu * cF);
-    pop_st<PT>(out, base + (size_t)i * n + idx, f[i] + om * (feq - f[i]) + src);
+    f[i] = f[i] + om * (feq - f[i]) + src;
+  }
+}
+
+// Stencil inputs of one site's update: the stress components and mu at the four
+// neighbours (E, W: x +- 1; N, S: y +- 1) and phi at the site.
+struct SiteStencil {
+  float xxE, xxW, yyN, yyS, sE, sW, sN, sS, aE, aW, aN, aS, muE, muW, muN, muS, phi;
+};
+
+// Forces, Guo velocities with the drag implicit, and (COLLIDE) both collisions of
+// one site, with fa, fp its pulled populations (replaced by post-collision values).
+// uo receives (u_a,x, u_a,y, u_c,x, u_c,y) when colliding, else the density
+// deviations and velocities (rho_a - rho0, rho_p - rho0, u_a,x, u_a,y, u_p,x, u_p,y).
+template <bool COLLIDE>
+__device__ __forceinline__ void site_update(const DevParams& P, float fa[9], float fp[9], const SiteStencil& t,
+                                            float uo[6]) {
+  // F_i = d_j sigma_ij with sigma_xy = s + a, sigma_yx = s - a
+  const float Fx = 0.5f * (t.xxE - t.xxW) + 0.5f * ((t.sN + t.aN) - (t.sS + t.aS));
+  const float Fy = 0.5f * ((t.sE - t.aE) - (t.sW - t.aW)) + 0.5f * (t.yyN - t.yyS);
+  const float pC = t.phi;
+  const float c1 = 0.5f * (1.f + pC), c2 = 0.5f * (1.f - pC);
+  // capillary force -phi grad(mu), shared c1 : c2
+  const float fchx = -pC * 0.5f * (t.muE - t.muW);
+  const float fchy = -pC * 0.5f * (t.muN - t.muS);
+  const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
+  const float Gpx = c2 * fchx, Gpy = c2 * fchy;
+  float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    dra += fa[i];
+    drp += fp[i];
+    if (CX[i] != 0) { mxa += CX[i] * fa[i]; mxp += CX[i] * fp[i]; }
+    if (CY[i] != 0) { mya += CY[i] * fa[i]; myp += CY[i] * fp[i]; }
+  }
+  const float rho_a = P.rho0 + dra, rho_p = P.rho0 + drp;
+  // per component [[rho_a + g, -g], [-g, rho_p + g]] [u_a; u_p] = [m_a + G_a/2; m_p + G_p/2]
+  const float g = 0.5f * P.gamma * c1 * c2;
+  const float inv = 1.f / (rho_a * rho_p + g * (rho_a + rho_p));
+  const float bax = mxa + 0.5f * Gax, bay = mya + 0.5f * Gay;
+  const float bpx = mxp + 0.5f * Gpx, bpy = myp + 0.5f * Gpy;
+  const float uax = ((rho_p + g) * bax + g * bpx) * inv;
+  const float uay = ((rho_p + g) * bay + g * bpy) * inv;
+  const float upx = (g * bax + (rho_a + g) * bpx) * inv;
+  const float upy = (g * bay + (rho_a + g) * bpy) * inv;
+  if (!COLLIDE) {
+    uo[0] = dra;  // density deviations: rho0 is added in float64 by the reader
+    uo[1] = drp;
+    uo[2] = uax;
+    uo[3] = uay;
+    uo[4] = upx;
+    uo[5] = upy;
+  } else {
+    const float fdx = 2.f * g * (upx - uax), fdy = 2.f * g * (upy - uay);
+    collide_fluid(fa, dra, uax, uay, Gax + fdx, Gay + fdy, P.om_a, P.gk_a, P.rho0);
+    collide_fluid(fp, drp, upx, upy, Gpx - fdx, Gpy - fdy, P.om_p, P.gk_p, P.rho0);
+    uo[0] = uax;
+    uo[1] = uay;
+    uo[2] = c1 * uax + c2 * upx;
+    uo[3] = c1 * uay + c2 * upy;
   }
 }
 
@@ -186,7 +244,26 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
   const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
   const int x0 = (tile % gx) * CT_X, y0 = (tile / gx) * CT_Y;
 
-  // 1. pull both population sets of this thread's sites: f_i(x) = f*_i(x - c_i)
+  // 1. phi, Qxx, Qxy of the tile with a halo of 2, loaded first: the LDS writes in
+  //    step 3 then wait for these loads only, and the population pulls issued in
+  //    step 2 stay in flight through the stress evaluation
+  constexpr int NS = PX * PY, KS = (NS + CT_THREADS - 1) / CT_THREADS;
+  float sv[KS][3];
+  {
+    const bool one_wrap = nx > CT_X && ny > PY;  // halo offsets need at most one periodic shift
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int c = min((int)threadIdx.x + k * CT_THREADS, NS - 1);
+      const int cy = c / PX, cx = c - cy * PX;
+      const int gy = y0 - 2 + cy, gxx = x0 - 2 + cx;
+      const int g = (one_wrap ? wrapi(gy, ny) : wrap_any(gy, ny)) * nx +
+                    (one_wrap ? wrapi(gxx, nx) : wrap_any(gxx, nx));
+      sv[k][0] = in.phi[g];
+      sv[k][1] = in.q[g];
+      sv[k][2] = in.q[n + g];
+    }
+  }
+  // 2. pull both population sets of this thread's sites: f_i(x) = f*_i(x - c_i)
   float fa[CT_SITES][9], fp[CT_SITES][9];
   const int x = x0 + tx;
   const bool xin = x < nx;
@@ -205,13 +282,15 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
       fp[s][i] = pop_ld<PT>(in.f, (size_t)(9 + i) * n + sy + sx);
     }
   }
-  // 2. stage phi, Qxx, Qxy on the tile with a halo of 2
-  for (int c = threadIdx.x; c < PX * PY; c += CT_THREADS) {
-    const int cy = c / PX, cx = c - cy * PX;
-    const int g = wrap_any(y0 - 2 + cy, ny) * nx + wrap_any(x0 - 2 + cx, nx);
-    sph[cy][cx] = in.phi[g];
-    sqx[cy][cx] = in.q[g];
-    sqy[cy][cx] = in.q[n + g];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int c = (int)threadIdx.x + k * CT_THREADS;
+    if (c < NS) {
+      const int cy = c / PX, cx = c - cy * PX;
+      sph[cy][cx] = sv[k][0];
+      sqx[cy][cx] = sv[k][1];
+      sqy[cy][cx] = sv[k][2];
+    }
   }
   __syncthreads();
   // 3. chemical potential and nematic stress on the tile plus a halo of 1
@@ -236,53 +315,25 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
     const int y = y0 + ly;
     if (!xin || y >= ny) continue;
     const int sy = ly + 1, sx = tx + 1;
-    // F_i = d_j sigma_ij with sigma_xy = s + a, sigma_yx = s - a
-    const float Fx = 0.5f * (sxx[sy][sx + 1] - sxx[sy][sx - 1]) +
-                     0.5f * ((ssy[sy + 1][sx] + san[sy + 1][sx]) - (ssy[sy - 1][sx] + san[sy - 1][sx]));
-    const float Fy = 0.5f * ((ssy[sy][sx + 1] - san[sy][sx + 1]) - (ssy[sy][sx - 1] - san[sy][sx - 1])) +
-                     0.5f * (syy[sy + 1][sx] - syy[sy - 1][sx]);
-    const float pC = sph[ly + 2][tx + 2];
-    const float c1 = 0.5f * (1.f + pC), c2 = 0.5f * (1.f - pC);
-    // capillary force -phi grad(mu), shared c1 : c2
-    const float fchx = -pC * 0.5f * (smu[sy][sx + 1] - smu[sy][sx - 1]);
-    const float fchy = -pC * 0.5f * (smu[sy + 1][sx] - smu[sy - 1][sx]);
-    const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
-    const float Gpx = c2 * fchx, Gpy = c2 * fchy;
-    float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      dra += fa[s][i];
-      drp += fp[s][i];
-      if (CX[i] != 0) { mxa += CX[i] * fa[s][i]; mxp += CX[i] * fp[s][i]; }
-      if (CY[i] != 0) { mya += CY[i] * fa[s][i]; myp += CY[i] * fp[s][i]; }
-    }
-    const float rho_a = P.rho0 + dra, rho_p = P.rho0 + drp;
-    // per component [[rho_a + g, -g], [-g, rho_p + g]] [u_a; u_p] = [m_a + G_a/2; m_p + G_p/2]
-    const float g = 0.5f * P.gamma * c1 * c2;
-    const float inv = 1.f / (rho_a * rho_p + g * (rho_a + rho_p));
-    const float bax = mxa + 0.5f * Gax, bay = mya + 0.5f * Gay;
-    const float bpx = mxp + 0.5f * Gpx, bpy = myp + 0.5f * Gpy;
-    const float uax = ((rho_p + g) * bax + g * bpx) * inv;
-    const float uay = ((rho_p + g) * bay + g * bpy) * inv;
-    const float upx = (g * bax + (rho_a + g) * bpx) * inv;
-    const float upy = (g * bay + (rho_a + g) * bpy) * inv;
+    const SiteStencil t = {sxx[sy][sx + 1], sxx[sy][sx - 1], syy[sy + 1][sx], syy[sy - 1][sx],
+                           ssy[sy][sx + 1], ssy[sy][sx - 1], ssy[sy + 1][sx], ssy[sy - 1][sx],
+                           san[sy][sx + 1], san[sy][sx - 1], san[sy + 1][sx], san[sy - 1][sx],
+                           smu[sy][sx + 1], smu[sy][sx - 1], smu[sy + 1][sx], smu[sy - 1][sx],
+                           sph[ly + 2][tx + 2]};
+    float uo[6];
+    site_update<!FIELDS>(P, fa[s], fp[s], t, uo);
     const int idx = y * nx + x;
     if (FIELDS) {
-      uout[idx] = dra;  // density deviations: rho0 is added in float64 by the reader
-      uout[n + idx] = drp;
-      uout[2 * n + idx] = uax;
-      uout[3 * n + idx] = uay;
-      uout[4 * n + idx] = upx;
-      uout[5 * n + idx] = upy;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) uout[c * n + idx] = uo[c];
     } else {
-      const float fdx = 2.f * g * (upx - uax), fdy = 2.f * g * (upy - uay);
-      collide_fluid<PT>(fa[s], dra, uax, uay, Gax + fdx, Gay + fdy, P.om_a, P.gk_a, P.rho0, fout, 0, n, idx);
-      collide_fluid<PT>(fp[s], drp, upx, upy, Gpx - fdx, Gpy - fdy, P.om_p, P.gk_p, P.rho0, fout,
-                        (size_t)9 * n, n, idx);
-      uout[idx] = uax;
-      uout[n + idx] = uay;
-      uout[2 * n + idx] = c1 * uax + c2 * upx;
-      uout[3 * n + idx] = c1 * uay + c2 * upy;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        pop_st<PT>(fout, (size_t)i * n + idx, fa[s][i]);
+        pop_st<PT>(fout, (size_t)(9 + i) * n + idx, fp[s][i]);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) uout[c * n + idx] = uo[c];
     }
   }
 }

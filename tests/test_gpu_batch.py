@@ -49,8 +49,8 @@ def test_fused_substeps_match_per_substep_launches(gpu, n_sub, nx, ny):
     p = base_params(nx, ny, zeta=0.03, lam=1.2, n_sub=n_sub)
     ic = initial_fields(nx, ny, seed=30 + n_sub, phi_noise=0.5, S0=0.3)
     ref = single(p, ic, 12, (2, 4)).get_state()
-    for f in (16, 32, 162, 163, 165):
-        assert np.array_equal(single(p, ic, 12, (2, f)).get_state(), ref), f
+    for shape in ((2, 16), (2, 32), (2, 162), (2, 163), (2, 165), (1, 165)):
+        assert np.array_equal(single(p, ic, 12, shape).get_state(), ref), shape
 
 
 def test_autotune_keeps_state(gpu):

@@ -48,22 +48,47 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const
   const int b = blockIdx.x / (tiles_x * tiles_y), t = blockIdx.x % (tiles_x * tiles_y);
   const int y0 = (t / tiles_x) * kTile, x0 = (t % tiles_x) * kTile;
   const int tid = threadIdx.x;
-  // stage the input tile (periodic halo) and the weights, 4 channels per load
-  constexpr int GP = CI / 4;
-  for (int i = tid; i < kHalo * kHalo * GP; i += 256) {
+  // stage the input tile (periodic halo) and the weights, 4 channels per load; all
+  // loads of a thread are issued before its first LDS write, so the block waits
+  // for one memory latency instead of one per load
+  constexpr int GP = CI / 4, NP = kHalo * kHalo * GP, KP = (NP + 255) / 256;
+  constexpr int GW = 9 * CI / 4, NWT = CO * GW, KW = (NWT + 255) / 256;
+  uint2 pv[KP], wv[KW];
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int i = min(tid + 256 * k, NP - 1);
     const int pix = i / GP, g = i - pix * GP;
     const int py = pix / kHalo, px = pix - py * kHalo;
     const int gy = wrap(y0 + py - 1, H), gx = wrap(x0 + px - 1, W);
-    const uint2 v = *reinterpret_cast<const uint2*>(in + (((size_t)b * H + gy) * W + gx) * CI + 4 * g);
-    *reinterpret_cast<uint2*>(&patch[pix * PS + 4 * g]) = v;
+    pv[k] = *reinterpret_cast<const uint2*>(in + (((size_t)b * H + gy) * W + gx) * CI + 4 * g);
   }
-  constexpr int GW = 9 * CI / 4;
-  for (int i = tid; i < CO * GW; i += 256) {
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = min(tid + 256 * k, NWT - 1);
     const int o = i / GW, g = i - o * GW;
-    *reinterpret_cast<uint2*>(&wts[o * WS + 4 * g]) = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
+    wv[k] = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
+  }
+  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
+  float bias_c[NT];
+#pragma unroll
+  for (int n = 0; n < NT; ++n) bias_c[n] = (MODE == kSilu || MODE == kLinear) ? bias[n * 16 + li] : 0.f;
+#pragma unroll
+  for (int k = 0; k < KP; ++k) {
+    const int i = tid + 256 * k;
+    if (i < NP) {
+      const int pix = i / GP, g = i - pix * GP;
+      *reinterpret_cast<uint2*>(&patch[pix * PS + 4 * g]) = pv[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int i = tid + 256 * k;
+    if (i < NWT) {
+      const int o = i / GW, g = i - o * GW;
+      *reinterpret_cast<uint2*>(&wts[o * WS + 4 * g]) = wv[k];
+    }
   }
   __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
   f32x4 acc[4][NT];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -102,11 +127,11 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const
         const size_t o = (((size_t)b * H + y) * W + x0 + 4 * lg + v) * CO + c;
         const float s = acc[m][n][v];
         if (MODE == kSilu) {
-          const float z = s + bias[c];
+          const float z = s + bias_c[n];
           if (out_f) out_f[o] = z;
           out_bf[o] = to_bf16(z * sigmoid(z));
         } else if (MODE == kLinear) {
-          out_f[o] = s + bias[c];
+          out_f[o] = s + bias_c[n];
         } else {
           const float z = z_below[o];
           const float sg = sigmoid(z);

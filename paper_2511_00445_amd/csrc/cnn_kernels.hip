@@ -23,25 +23,37 @@ __device__ __forceinline__ bf16 to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
-
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // ---------------------------------------------------------------------------
 // Convolution.  A block computes a 16 x 16 tile of sites for all CO output
-// channels: M = 256 sites (wave w owns rows 4w..4w+3, one 16-site M-tile each),
-// N = CO, K = 9 taps x CI channels, 16 channels of one tap per MFMA.  The input
-// tile with a halo of 1 and the layer's weights are staged in LDS; the pixel
-// and weight strides carry 4 extra bf16 so the 8-byte fragment reads of 16
-// lanes fall in distinct banks.
+// channels as an implicit GEMM with the weights as the left operand: M = CO
+// (16 channels per M-tile), N = 256 sites (wave w owns tile rows 4w..4w+3, one
+// 16-site N-tile each), K = 9 taps x CI channels in tap-major order, 32 per
+// v_mfma_f32_16x16x32_bf16 (a K remainder of 16 takes the 16x16x16 form).  A
+// dot product does not depend on which k-slot of the instruction carries which
+// k, so lane group g (lanes 16g..16g+15) takes the 8 consecutive k of its slot
+// range: one 16-byte LDS read per fragment, never straddling a tap (taps are
+// multiples of 16 channels).  The result D[4g+v][l%16] gives each lane four
+// consecutive channels of one site, stored as one 8-byte (bf16) or 16-byte
+// (fp32) access.  The input tile with a halo of 1 and the weights are staged in
+// LDS with strides of 8 extra bf16, so the 16-byte reads of 8 lanes at a time
+// fall in distinct banks.
 // ---------------------------------------------------------------------------
 constexpr int kHalo = kTile + 2;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// silu(z) = z sigmoid(z) and its derivative factor sigmoid(z) (1 + z (1 - sigmoid(z)));
+// the reciprocal is the hardware one (1 ulp), far below the bf16 rounding that follows.
+__device__ __forceinline__ float fast_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
 template <int CI, int CO, int MODE>
 __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
                                               const float* __restrict__ bias, const float* __restrict__ z_below,
                                               bf16* __restrict__ out_bf, float* __restrict__ out_f, int H, int W) {
-  constexpr int PS = CI + 4, WS = 9 * CI + 4, NT = CO / 16, KC = CI / 16;
+  constexpr int PS = CI + 8, WS = 9 * CI + 8, NT = CO / 16;
+  constexpr int KTOT = 9 * CI, NC = KTOT / 32, REM = KTOT - 32 * NC;
+  static_assert(CI % 16 == 0 && CO % 16 == 0 && (REM == 0 || REM == 16), "k-blocks of 16 channels");
   __shared__ __attribute__((aligned(16))) bf16 patch[kHalo * kHalo * PS];
   __shared__ __attribute__((aligned(16))) bf16 wts[CO * WS];
   const int tiles_x = W / kTile, tiles_y = H / kTile;
@@ -69,9 +81,11 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const
     wv[k] = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
   }
   const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
-  float bias_c[NT];
+  float bias_c[NT][4];
 #pragma unroll
-  for (int n = 0; n < NT; ++n) bias_c[n] = (MODE == kSilu || MODE == kLinear) ? bias[n * 16 + li] : 0.f;
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bias_c[n][v] = (MODE == kSilu || MODE == kLinear) ? bias[n * 16 + 4 * lg + v] : 0.f;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
     const int i = tid + 256 * k;
@@ -89,54 +103,75 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const
     }
   }
   __syncthreads();
-  f32x4 acc[4][NT];
+  f32x4 acc[NT][4];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int n = 0; n < NT; ++n)
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-  for (int tap = 0; tap < 9; ++tap) {
+    for (int m = 0; m < 4; ++m) acc[n][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // LDS offset of the patch pixel under site (row 4 wave + m, column li) for tap (dy, dx)
+  const int site0 = (4 * wave) * kHalo + li;
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    const int k0 = 32 * j + 8 * lg;
+    const int tap = k0 / CI, c0 = k0 - tap * CI;
     const int dy = tap / 3, dx = tap - 3 * dy;
+    bf16x8 wa[NT], pb[4];
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      bf16x4 a[4], bw[NT];
+    for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x8*>(&wts[(n * 16 + li) * WS + k0]);
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int r = 4 * wave + m;  // tile row of this M-tile; site x = li
-        a[m] = *reinterpret_cast<const bf16x4*>(&patch[((r + dy) * kHalo + li + dx) * PS + kc * 16 + 4 * lg]);
-      }
+    for (int m = 0; m < 4; ++m)
+      pb[m] = *reinterpret_cast<const bf16x8*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
 #pragma unroll
-      for (int n = 0; n < NT; ++n)
-        bw[n] = *reinterpret_cast<const bf16x4*>(&wts[(n * 16 + li) * WS + tap * CI + kc * 16 + 4 * lg]);
+    for (int n = 0; n < NT; ++n)
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bw[n], acc[m][n], 0, 0, 0);
-    }
+      for (int m = 0; m < 4; ++m) acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[n], pb[m], acc[n][m], 0, 0, 0);
   }
-  // epilogue: D[4 lg + v][li] -> site x = 4 lg + v of tile row r, channel n * 16 + li
+  if constexpr (REM == 16) {
+    const int k0 = 32 * NC + 4 * lg;
+    const int tap = k0 / CI, c0 = k0 - tap * CI;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    bf16x4 wa[NT], pb[4];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x4*>(&wts[(n * 16 + li) * WS + k0]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      pb[m] = *reinterpret_cast<const bf16x4*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[n], pb[m], acc[n][m], 0, 0, 0);
+  }
+  // epilogue: D[4 lg + v][li] of acc[n][m] -> channel n * 16 + 4 lg + v of site (row 4 wave + m, x li)
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const int y = y0 + 4 * wave + m;
+    const size_t site = ((size_t)b * H + y0 + 4 * wave + m) * W + x0 + li;
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
-      const int c = n * 16 + li;
+      const size_t o = site * CO + n * 16 + 4 * lg;
+      if (MODE == kSilu) {
+        f32x4 z;
+        bf16x4 a;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const size_t o = (((size_t)b * H + y) * W + x0 + 4 * lg + v) * CO + c;
-        const float s = acc[m][n][v];
-        if (MODE == kSilu) {
-          const float z = s + bias_c[n];
-          if (out_f) out_f[o] = z;
-          out_bf[o] = to_bf16(z * sigmoid(z));
-        } else if (MODE == kLinear) {
-          out_f[o] = s + bias_c[n];
-        } else {
-          const float z = z_below[o];
-          const float sg = sigmoid(z);
-          out_bf[o] = to_bf16(s * (sg * (1.f + z * (1.f - sg))));
+        for (int v = 0; v < 4; ++v) {
+          z[v] = acc[n][m][v] + bias_c[n][v];
+          a[v] = (short)to_bf16(z[v] * fast_sigmoid(z[v]));
         }
+        if (out_f) *reinterpret_cast<f32x4*>(out_f + o) = z;
+        *reinterpret_cast<bf16x4*>(out_bf + o) = a;
+      } else if (MODE == kLinear) {
+        f32x4 y;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[v] = acc[n][m][v] + bias_c[n][v];
+        *reinterpret_cast<f32x4*>(out_f + o) = y;
+      } else {
+        const f32x4 z = *reinterpret_cast<const f32x4*>(z_below + o);
+        bf16x4 a;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float sg = fast_sigmoid(z[v]);
+          a[v] = (short)to_bf16(acc[n][m][v] * (sg * (1.f + z[v] * (1.f - sg))));
+        }
+        *reinterpret_cast<bf16x4*>(out_bf + o) = a;
       }
     }
   }

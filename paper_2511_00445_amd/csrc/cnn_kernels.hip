@@ -8,6 +8,8 @@
 // B[4(l/16)+v][l%16] and D[4(l/16)+v][l%16], v = 0..3.
 #include "cnn_internal.h"
 
+#include <algorithm>
+
 namespace tcnn {
 namespace {
 
@@ -47,38 +49,62 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // the reciprocal is the hardware one (1 ulp), far below the bf16 rounding that follows.
 __device__ __forceinline__ float fast_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
-template <int CI, int CO, int MODE>
-__global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
-                                              const float* __restrict__ bias, const float* __restrict__ z_below,
-                                              bf16* __restrict__ out_bf, float* __restrict__ out_f, int H, int W) {
-  constexpr int PS = CI + 8, WS = 9 * CI + 8, NT = CO / 16;
-  constexpr int KTOT = 9 * CI, NC = KTOT / 32, REM = KTOT - 32 * NC;
-  static_assert(CI % 16 == 0 && CO % 16 == 0 && (REM == 0 || REM == 16), "k-blocks of 16 channels");
-  __shared__ __attribute__((aligned(16))) bf16 patch[kHalo * kHalo * PS];
-  __shared__ __attribute__((aligned(16))) bf16 wts[CO * WS];
-  const int tiles_x = W / kTile, tiles_y = H / kTile;
-  const int b = blockIdx.x / (tiles_x * tiles_y), t = blockIdx.x % (tiles_x * tiles_y);
-  const int y0 = (t / tiles_x) * kTile, x0 = (t % tiles_x) * kTile;
-  const int tid = threadIdx.x;
-  // stage the input tile (periodic halo) and the weights, 4 channels per load; all
-  // loads of a thread are issued before its first LDS write, so the block waits
-  // for one memory latency instead of one per load
-  constexpr int GP = CI / 4, NP = kHalo * kHalo * GP, KP = (NP + 255) / 256;
-  constexpr int GW = 9 * CI / 4, NWT = CO * GW, KW = (NWT + 255) / 256;
-  uint2 pv[KP], wv[KW];
+// Input tile of 16 x 16 sites with its periodic halo: this thread's 8-byte pieces.
+template <int CI, int KP>
+__device__ __forceinline__ void load_patch(const bf16* __restrict__ in, int t, int H, int W, uint2 (&pv)[KP]) {
+  constexpr int GP = CI / 4, NP = kHalo * kHalo * GP;
+  const int tiles_x = W / kTile, tiles_img = tiles_x * (H / kTile);
+  const int b = t / tiles_img, tt = t - b * tiles_img;
+  const int y0 = (tt / tiles_x) * kTile, x0 = (tt % tiles_x) * kTile;
 #pragma unroll
   for (int k = 0; k < KP; ++k) {
-    const int i = min(tid + 256 * k, NP - 1);
+    const int i = min((int)threadIdx.x + 256 * k, NP - 1);
     const int pix = i / GP, g = i - pix * GP;
     const int py = pix / kHalo, px = pix - py * kHalo;
     const int gy = wrap(y0 + py - 1, H), gx = wrap(x0 + px - 1, W);
     pv[k] = *reinterpret_cast<const uint2*>(in + (((size_t)b * H + gy) * W + gx) * CI + 4 * g);
   }
+}
+
+// Persistent blocks: a block stages the layer's weights once and walks the tiles
+// t = blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's input is loaded
+// into registers while the matrix cores work on the current one.
+template <int CI, int CO, int MODE>
+__global__ void __launch_bounds__(256, 2) k_conv(const bf16* __restrict__ in, const bf16* __restrict__ w,
+                                              const float* __restrict__ bias, const float* __restrict__ z_below,
+                                              bf16* __restrict__ out_bf, float* __restrict__ out_f, int B, int H,
+                                              int W) {
+  constexpr int PS = CI + 8, WS = 9 * CI + 8, NT = CO / 16;
+  constexpr int KTOT = 9 * CI, NC = KTOT / 32, REM = KTOT - 32 * NC;
+  static_assert(CI % 16 == 0 && CO % 16 == 0 && (REM == 0 || REM == 16), "k-blocks of 16 channels");
+  __shared__ __attribute__((aligned(16))) bf16 patch[kHalo * kHalo * PS];
+  __shared__ __attribute__((aligned(16))) bf16 wts[CO * WS];
+  const int tiles_x = W / kTile, tiles_img = tiles_x * (H / kTile), tiles = B * tiles_img;
+  int t = blockIdx.x;
+  if (t >= tiles) return;  // whole block, before any barrier
+  const int tid = threadIdx.x;
+  constexpr int GP = CI / 4, NP = kHalo * kHalo * GP, KP = (NP + 255) / 256;
+  constexpr int GW = 9 * CI / 4, NWT = CO * GW, KW = (NWT + 255) / 256;
+  // stage the weights and the first tile; all loads are issued before the first
+  // LDS write, so the block waits for one memory latency
+  uint2 pv[KP];
+  {
+    uint2 wv[KW];
 #pragma unroll
-  for (int k = 0; k < KW; ++k) {
-    const int i = min(tid + 256 * k, NWT - 1);
-    const int o = i / GW, g = i - o * GW;
-    wv[k] = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
+    for (int k = 0; k < KW; ++k) {
+      const int i = min(tid + 256 * k, NWT - 1);
+      const int o = i / GW, g = i - o * GW;
+      wv[k] = *reinterpret_cast<const uint2*>(w + (size_t)o * 9 * CI + 4 * g);
+    }
+    load_patch<CI, KP>(in, t, H, W, pv);
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      const int i = tid + 256 * k;
+      if (i < NWT) {
+        const int o = i / GW, g = i - o * GW;
+        *reinterpret_cast<uint2*>(&wts[o * WS + 4 * g]) = wv[k];
+      }
+    }
   }
   const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lg = lane >> 4;
   float bias_c[NT][4];
@@ -86,94 +112,97 @@ __global__ void __launch_bounds__(256) k_conv(const bf16* __restrict__ in, const
   for (int n = 0; n < NT; ++n)
 #pragma unroll
     for (int v = 0; v < 4; ++v) bias_c[n][v] = (MODE == kSilu || MODE == kLinear) ? bias[n * 16 + 4 * lg + v] : 0.f;
-#pragma unroll
-  for (int k = 0; k < KP; ++k) {
-    const int i = tid + 256 * k;
-    if (i < NP) {
-      const int pix = i / GP, g = i - pix * GP;
-      *reinterpret_cast<uint2*>(&patch[pix * PS + 4 * g]) = pv[k];
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < KW; ++k) {
-    const int i = tid + 256 * k;
-    if (i < NWT) {
-      const int o = i / GW, g = i - o * GW;
-      *reinterpret_cast<uint2*>(&wts[o * WS + 4 * g]) = wv[k];
-    }
-  }
-  __syncthreads();
-  f32x4 acc[NT][4];
-#pragma unroll
-  for (int n = 0; n < NT; ++n)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) acc[n][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // LDS offset of the patch pixel under site (row 4 wave + m, column li) for tap (dy, dx)
+  // LDS offset of the patch pixel under site (row 4 wave + m, column li) at tap (0, 0)
   const int site0 = (4 * wave) * kHalo + li;
+  for (;;) {
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    const int k0 = 32 * j + 8 * lg;
-    const int tap = k0 / CI, c0 = k0 - tap * CI;
-    const int dy = tap / 3, dx = tap - 3 * dy;
-    bf16x8 wa[NT], pb[4];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x8*>(&wts[(n * 16 + li) * WS + k0]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      pb[m] = *reinterpret_cast<const bf16x8*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
-#pragma unroll
-    for (int n = 0; n < NT; ++n)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[n], pb[m], acc[n][m], 0, 0, 0);
-  }
-  if constexpr (REM == 16) {
-    const int k0 = 32 * NC + 4 * lg;
-    const int tap = k0 / CI, c0 = k0 - tap * CI;
-    const int dy = tap / 3, dx = tap - 3 * dy;
-    bf16x4 wa[NT], pb[4];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x4*>(&wts[(n * 16 + li) * WS + k0]);
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      pb[m] = *reinterpret_cast<const bf16x4*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
-#pragma unroll
-    for (int n = 0; n < NT; ++n)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[n], pb[m], acc[n][m], 0, 0, 0);
-  }
-  // epilogue: D[4 lg + v][li] of acc[n][m] -> channel n * 16 + 4 lg + v of site (row 4 wave + m, x li)
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const size_t site = ((size_t)b * H + y0 + 4 * wave + m) * W + x0 + li;
-#pragma unroll
-    for (int n = 0; n < NT; ++n) {
-      const size_t o = site * CO + n * 16 + 4 * lg;
-      if (MODE == kSilu) {
-        f32x4 z;
-        bf16x4 a;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          z[v] = acc[n][m][v] + bias_c[n][v];
-          a[v] = (short)to_bf16(z[v] * fast_sigmoid(z[v]));
-        }
-        if (out_f) *reinterpret_cast<f32x4*>(out_f + o) = z;
-        *reinterpret_cast<bf16x4*>(out_bf + o) = a;
-      } else if (MODE == kLinear) {
-        f32x4 y;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) y[v] = acc[n][m][v] + bias_c[n][v];
-        *reinterpret_cast<f32x4*>(out_f + o) = y;
-      } else {
-        const f32x4 z = *reinterpret_cast<const f32x4*>(z_below + o);
-        bf16x4 a;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float sg = fast_sigmoid(z[v]);
-          a[v] = (short)to_bf16(acc[n][m][v] * (sg * (1.f + z[v] * (1.f - sg))));
-        }
-        *reinterpret_cast<bf16x4*>(out_bf + o) = a;
+    for (int k = 0; k < KP; ++k) {
+      const int i = tid + 256 * k;
+      if (i < NP) {
+        const int pix = i / GP, g = i - pix * GP;
+        *reinterpret_cast<uint2*>(&patch[pix * PS + 4 * g]) = pv[k];
       }
     }
+    __syncthreads();
+    const int tn = t + (int)gridDim.x;
+    if (tn < tiles) load_patch<CI, KP>(in, tn, H, W, pv);
+    f32x4 acc[NT][4];
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[n][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int k0 = 32 * j + 8 * lg;
+      const int tap = k0 / CI, c0 = k0 - tap * CI;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      bf16x8 wa[NT], pb[4];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x8*>(&wts[(n * 16 + li) * WS + k0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        pb[m] = *reinterpret_cast<const bf16x8*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[n], pb[m], acc[n][m], 0, 0, 0);
+    }
+    if constexpr (REM == 16) {
+      const int k0 = 32 * NC + 4 * lg;
+      const int tap = k0 / CI, c0 = k0 - tap * CI;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      bf16x4 wa[NT], pb[4];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) wa[n] = *reinterpret_cast<const bf16x4*>(&wts[(n * 16 + li) * WS + k0]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        pb[m] = *reinterpret_cast<const bf16x4*>(&patch[(site0 + (m + dy) * kHalo + dx) * PS + c0]);
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+          acc[n][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wa[n], pb[m], acc[n][m], 0, 0, 0);
+    }
+    // epilogue: D[4 lg + v][li] of acc[n][m] -> channel n * 16 + 4 lg + v of site (row 4 wave + m, x li)
+    const int b = t / tiles_img, tt = t - b * tiles_img;
+    const int y0 = (tt / tiles_x) * kTile, x0 = (tt % tiles_x) * kTile;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const size_t site = ((size_t)b * H + y0 + 4 * wave + m) * W + x0 + li;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const size_t o = site * CO + n * 16 + 4 * lg;
+        if (MODE == kSilu) {
+          f32x4 z;
+          bf16x4 a;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            z[v] = acc[n][m][v] + bias_c[n][v];
+            a[v] = (short)to_bf16(z[v] * fast_sigmoid(z[v]));
+          }
+          if (out_f) *reinterpret_cast<f32x4*>(out_f + o) = z;
+          *reinterpret_cast<bf16x4*>(out_bf + o) = a;
+        } else if (MODE == kLinear) {
+          f32x4 y;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) y[v] = acc[n][m][v] + bias_c[n][v];
+          *reinterpret_cast<f32x4*>(out_f + o) = y;
+        } else {
+          const f32x4 z = *reinterpret_cast<const f32x4*>(z_below + o);
+          bf16x4 a;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float sg = fast_sigmoid(z[v]);
+            a[v] = (short)to_bf16(acc[n][m][v] * (sg * (1.f + z[v] * (1.f - sg))));
+          }
+          *reinterpret_cast<bf16x4*>(out_bf + o) = a;
+        }
+      }
+    }
+    if (tn >= tiles) break;
+    t = tn;
+    __syncthreads();  // every wave is done with this tile's patch
   }
 }
 
@@ -206,18 +235,51 @@ __global__ void __launch_bounds__(256) k_weight_grad(const bf16* __restrict__ g,
     for (int j = 0; j < NW; ++j) acc[m][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bacc = 0.f;  // thread (co = tid % CO, part = tid / CO) sums sites part*64 .. +63
   const int bco = tid % CO, bpart = tid / CO;
+  // 8-byte pieces (4 channels) of the gradient tile and of the input tile with its halo
+  constexpr int GG = CO / 4, NG = kTile * kTile * GG, KG = (NG + 255) / 256;
+  constexpr int GA = CI / 4, NA = kHalo * kHalo * GA, KA = (NA + 255) / 256;
   for (int t = blockIdx.x; t < tiles; t += gridDim.x) {
     const int b = t / (tiles_x * tiles_y), r = t % (tiles_x * tiles_y);
     const int y0 = (r / tiles_x) * kTile, x0 = (r % tiles_x) * kTile;
-    __syncthreads();  // previous tile's reads are done
-    for (int i = tid; i < kTile * kTile * CO; i += 256) {
-      const int s = i / CO, c = i - s * CO;
-      gT[c * GS + s] = g[(((size_t)b * H + y0 + s / kTile) * W + x0 + s % kTile) * CO + c];
+    // all loads of the tile are issued before the first LDS write
+    uint2 gv[KG], av[KA];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int i = min(tid + 256 * k, NG - 1);
+      const int s = i / GG, c4 = i - s * GG;
+      gv[k] = *reinterpret_cast<const uint2*>(g + (((size_t)b * H + y0 + s / kTile) * W + x0 + s % kTile) * CO + 4 * c4);
     }
-    for (int i = tid; i < kHalo * kHalo * CI; i += 256) {
-      const int pix = i / CI, c = i - pix * CI;
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+      const int i = min(tid + 256 * k, NA - 1);
+      const int pix = i / GA, c4 = i - pix * GA;
       const int py = pix / kHalo, px = pix - py * kHalo;
-      aT[(c * kHalo + py) * AS + px] = a[(((size_t)b * H + wrap(y0 + py - 1, H)) * W + wrap(x0 + px - 1, W)) * CI + c];
+      av[k] = *reinterpret_cast<const uint2*>(
+          a + (((size_t)b * H + wrap(y0 + py - 1, H)) * W + wrap(x0 + px - 1, W)) * CI + 4 * c4);
+    }
+    __syncthreads();  // previous tile's reads are done
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const int i = tid + 256 * k;
+      if (i < NG) {
+        const int s = i / GG, c = 4 * (i - s * GG);
+        gT[c * GS + s] = (bf16)(gv[k].x & 0xffffu);
+        gT[(c + 1) * GS + s] = (bf16)(gv[k].x >> 16);
+        gT[(c + 2) * GS + s] = (bf16)(gv[k].y & 0xffffu);
+        gT[(c + 3) * GS + s] = (bf16)(gv[k].y >> 16);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+      const int i = tid + 256 * k;
+      if (i < NA) {
+        const int pix = i / GA, c = 4 * (i - pix * GA);
+        const int py = pix / kHalo, px = pix - py * kHalo;
+        aT[(c * kHalo + py) * AS + px] = (bf16)(av[k].x & 0xffffu);
+        aT[((c + 1) * kHalo + py) * AS + px] = (bf16)(av[k].x >> 16);
+        aT[((c + 2) * kHalo + py) * AS + px] = (bf16)(av[k].y & 0xffffu);
+        aT[((c + 3) * kHalo + py) * AS + px] = (bf16)(av[k].y >> 16);
+      }
     }
     __syncthreads();
     if (bpart < 4) {
@@ -267,23 +329,35 @@ __global__ void __launch_bounds__(256) k_weight_grad(const bf16* __restrict__ g,
   if (tid < CO) partial_b[(size_t)blockIdx.x * CO + tid] = (bsum[0][tid] + bsum[1][tid]) + (bsum[2][tid] + bsum[3][tid]);
 }
 
-// Sum of the block partials in block order into the natural layout of the real channels.
-__global__ void k_weight_grad_reduce(const float* __restrict__ partial, const float* __restrict__ partial_b,
-                                     int nblk, int ci, int co, int ci_real, int co_real, float* __restrict__ gW,
-                                     float* __restrict__ gb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nW = co_real * ci_real * 9;
-  if (i < nW) {
-    const int o = i / (ci_real * 9), rem = i - o * ci_real * 9, c = rem / 9, tap = rem - c * 9;
-    const size_t col = ((size_t)o * 9 + tap) * ci + c, stride = (size_t)co * 9 * ci;
-    float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += partial[k * stride + col];
-    gW[i] = s;
-  } else if (i < nW + co_real) {
-    const int o = i - nW;
-    float s = 0.f;
-    for (int k = 0; k < nblk; ++k) s += partial_b[(size_t)k * co + o];
-    gb[o] = s;
+// Sum of the block partials into the natural layout of the real channels.  A
+// block takes 32 columns (weight columns [co][9][ci], then the co bias entries);
+// eight thread groups each sum every eighth block partial in ascending order,
+// and the eight sums meet in a fixed tree, so the result is deterministic.
+__global__ void __launch_bounds__(256) k_weight_grad_reduce(const float* __restrict__ partial,
+                                                            const float* __restrict__ partial_b, int nblk, int ci,
+                                                            int co, int ci_real, int co_real, float* __restrict__ gW,
+                                                            float* __restrict__ gb) {
+  __shared__ float red[8][32];
+  const int lane = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int ncol = co * 9 * ci, ntot = ncol + co;
+  const int col = blockIdx.x * 32 + lane;
+  float s = 0.f;
+  if (col < ntot) {
+    const bool wcol = col < ncol;
+    const float* src = wcol ? partial + col : partial_b + (col - ncol);
+    const size_t stride = wcol ? (size_t)ncol : (size_t)co;
+    for (int k = grp; k < nblk; k += 8) s += src[(size_t)k * stride];
+  }
+  red[grp][lane] = s;
+  __syncthreads();
+  if (grp != 0 || col >= ntot) return;
+  const float t = ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])) +
+                  ((red[4][lane] + red[5][lane]) + (red[6][lane] + red[7][lane]));
+  if (col < ncol) {
+    const int o = col / (9 * ci), rem = col - o * 9 * ci, tap = rem / ci, c = rem - tap * ci;
+    if (o < co_real && c < ci_real) gW[(o * ci_real + c) * 9 + tap] = t;
+  } else if (col - ncol < co_real) {
+    gb[col - ncol] = t;
   }
 }
 
@@ -452,9 +526,18 @@ __global__ void __launch_bounds__(256) k_compare_final(const double* __restrict_
 // ---------------------------------------------------------------------------
 hipError_t launch_conv(int ci, int co, ConvMode mode, const bf16* in, const bf16* w, const float* bias,
                        const float* z_below, bf16* out_bf, float* out_f, int B, int H, int W, hipStream_t st) {
-  const dim3 grid((unsigned)(B * (H / kTile) * (W / kTile))), blk(256);
+  // two resident blocks per compute unit (the LDS of one block is about 80 KB)
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  const int tiles = B * (H / kTile) * (W / kTile);
+  const dim3 grid((unsigned)std::min(tiles, 2 * cus)), blk(256);
 #define TCNN_CONV(CI_, CO_, M_) \
-  hipLaunchKernelGGL((k_conv<CI_, CO_, M_>), grid, blk, 0, st, in, w, bias, z_below, out_bf, out_f, H, W)
+  hipLaunchKernelGGL((k_conv<CI_, CO_, M_>), grid, blk, 0, st, in, w, bias, z_below, out_bf, out_f, B, H, W)
   if (ci == kPadIO && co == kHidden && mode == kSilu) TCNN_CONV(kPadIO, kHidden, kSilu);
   else if (ci == kHidden && co == kHidden && mode == kSilu) TCNN_CONV(kHidden, kHidden, kSilu);
   else if (ci == kHidden && co == kPadIO && mode == kLinear) TCNN_CONV(kHidden, kPadIO, kLinear);
@@ -484,8 +567,8 @@ hipError_t launch_weight_grad(int ci, int co, int ci_real, int co_real, const bf
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n = co_real * ci_real * 9 + co_real;
-  hipLaunchKernelGGL(k_weight_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, st, partial, partial_b, nblk, ci, co,
+  const int n = co * 9 * ci + co;  // padded weight columns, then the bias
+  hipLaunchKernelGGL(k_weight_grad_reduce, dim3((n + 31) / 32), dim3(256), 0, st, partial, partial_b, nblk, ci, co,
                      ci_real, co_real, gW, gb);
   return hipGetLastError();
 }

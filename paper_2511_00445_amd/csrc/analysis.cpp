@@ -85,14 +85,18 @@ int finish(tfan_analysis* a) {
   return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "analysis");
 }
 
-// Pack and forward-transform the three complex fields.
+// Pack and forward-transform the three complex fields; the transforms land
+// transposed in scratch, z[0] and z[1], and the powers (pE, pS, w0, w1) keep that
+// layout (every later use is symmetric in the two axes).  z[2] is free afterwards.
 int transforms(tfan_analysis* a, const float* s) {
   float2* z[3] = {a->at<float2>(a->p.z[0]), a->at<float2>(a->p.z[1]), a->at<float2>(a->p.z[2])};
+  float2* scratch = a->at<float2>(a->p.scratch);
   hipError_t e = tana::launch_pack(s, a->n, z[0], z[1], z[2], a->stream);
-  for (int k = 0; k < 3 && e == hipSuccess; ++k)
-    e = tana::launch_fft2(z[k], a->at<float2>(a->p.scratch), a->n, a->logn, false, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[0], scratch, a->n, a->logn, false, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[1], z[0], a->n, a->logn, false, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[2], z[1], a->n, a->logn, false, a->stream);
   if (e == hipSuccess)
-    e = tana::launch_power(z[0], z[1], z[2], a->n, a->at<float>(a->p.pE), a->at<float>(a->p.pS),
+    e = tana::launch_power(scratch, z[0], z[1], a->n, a->at<float>(a->p.pE), a->at<float>(a->p.pS),
                            a->at<float2>(a->p.w[0]), a->at<float2>(a->p.w[1]), a->stream);
   return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "transforms");
 }
@@ -154,15 +158,16 @@ int tfan_analysis_correlations(tfan_analysis* a, const float* s, double* Cuu, do
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
   int rc = transforms(a, s);
   if (rc) return rc;
-  float2* w0 = a->at<float2>(a->p.w[0]);
-  float2* w1 = a->at<float2>(a->p.w[1]);
-  hipError_t e = tana::launch_fft2(w0, a->at<float2>(a->p.scratch), a->n, a->logn, true, a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2(w1, a->at<float2>(a->p.scratch), a->n, a->logn, true, a->stream);
+  // inverse transforms of the (transposed) powers come out in natural layout
+  float2* c0 = a->at<float2>(a->p.z[2]);
+  float2* c1 = a->at<float2>(a->p.scratch);
+  hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->stream);
   const int ns = a->ns;
   double* out = a->at<double>(a->p.out);
   if (e == hipSuccess)
-    e = tana::launch_shells(reinterpret_cast<const float*>(w0), reinterpret_cast<const float*>(w0) + 1,
-                            reinterpret_cast<const float*>(w1), 2, a->n, ns, true, a->at<double>(a->p.partial),
+    e = tana::launch_shells(reinterpret_cast<const float*>(c0), reinterpret_cast<const float*>(c0) + 1,
+                            reinterpret_cast<const float*>(c1), 2, a->n, ns, true, a->at<double>(a->p.partial),
                             a->at<int>(a->p.pcount), out, a->stream);
   if (e != hipSuccess) return hip_fail(a, e, "correlations");
   if ((rc = copy_out(a, Cuu, out, ns)) || (rc = copy_out(a, Cww, out + ns, ns)) ||

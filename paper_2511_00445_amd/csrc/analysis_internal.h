@@ -7,9 +7,13 @@ namespace tana {
 
 // za = phi + i omega_c, zb = u_c, zc = Qxx + i Qxy from an exported state [7][n][n].
 hipError_t launch_pack(const float* state, int n, float2* za, float2* zb, float2* zc, hipStream_t st);
-// In-place 2D FFT (unnormalised; inverse = conjugate twiddles) of an n x n complex
-// array, n = 2^logn, using `scratch` (n x n) for the transposes.
-hipError_t launch_fft2(float2* z, float2* scratch, int n, int logn, bool inverse, hipStream_t st);
+// 2D FFT (unnormalised; inverse = conjugate twiddles) of the n x n complex array
+// `in` (overwritten), n = 2^logn, written TRANSPOSED to `out` (out[x][y] = F[y][x]):
+// row transforms, one transpose, row transforms.  Power spectra and shell sums
+// are symmetric in the two axes, and the transposed-layout inverse of a
+// transposed array is the natural-layout inverse, so the second transpose of
+// each transform is never needed.
+hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, hipStream_t st);
 // Power spectra and the inverse-transform inputs of the correlations (see k_power).
 hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, int n, float* pE, float* pS,
                         float2* w0, float2* w1, hipStream_t st);

@@ -47,35 +47,66 @@ __global__ void k_pack(const float* __restrict__ s, int n, float2* __restrict__ 
   zc[i] = make_float2(s[n2 + i], s[2 * n2 + i]);
 }
 
-// Radix-2 FFT of every row (one block per row): bit-reversed load into LDS, then
-// log2(n) butterfly stages with twiddles w_k = exp(-+ 2 pi i k / n) from a table.
-// Unnormalised; INV uses the conjugate twiddles.
+// FFT of every row (one block per row), unnormalised; INV uses the conjugate
+// twiddles w_k = exp(+2 pi i k / n).  Bit-reversed load into LDS, then the radix-2
+// decimation-in-time stages in pairs: a thread takes four points, applies the
+// butterflies of two consecutive stages in registers and writes them back, so a
+// pair costs one LDS round trip and one barrier (an odd last stage runs alone).
+// The butterflies and twiddles are those of the plain radix-2 form, in the same
+// order.  LDS index i is stored at i + i / 32, spreading the bit-reversed writes
+// over the banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 5); }
+__device__ __forceinline__ void butterfly(float2& u, float2& v, float2 w) {
+  const float2 t = make_float2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+  const float2 a = u;
+  u = make_float2(a.x + t.x, a.y + t.y);
+  v = make_float2(a.x - t.x, a.y - t.y);
+}
 template <bool INV>
 __global__ void __launch_bounds__(256) k_fft_rows(float2* __restrict__ data, int n, int logn) {
   extern __shared__ float2 sm[];
   float2* buf = sm;
-  float2* tw = sm + n;
+  float2* tw = sm + n + (n >> 5);
   float2* row = data + (size_t)blockIdx.x * n;
-  for (int i = threadIdx.x; i < n; i += 256) buf[__brev((unsigned)i) >> (32 - logn)] = row[i];
+  for (int i = threadIdx.x; i < n; i += 256) buf[lds_pad(__brev((unsigned)i) >> (32 - logn))] = row[i];
   for (int k = threadIdx.x; k < n / 2; k += 256) {
     float sn, cs;
     sincospif(2.f * (float)k / (float)n, &sn, &cs);
     tw[k] = make_float2(cs, INV ? sn : -sn);
   }
   __syncthreads();
-  for (int lh = 0; lh < logn; ++lh) {
+  int lh = 0;
+  for (; lh + 1 < logn; lh += 2) {
+    const int half = 1 << lh, s1 = n >> (lh + 1), s2 = n >> (lh + 2);
+    for (int q = threadIdx.x; q < n / 4; q += 256) {
+      const int pos = q & (half - 1), grp = q >> lh;
+      const int i0 = (grp << (lh + 2)) + pos, i1 = i0 + half, i2 = i1 + half, i3 = i2 + half;
+      float2 a0 = buf[lds_pad(i0)], a1 = buf[lds_pad(i1)], a2 = buf[lds_pad(i2)], a3 = buf[lds_pad(i3)];
+      const float2 w1 = tw[pos * s1];
+      butterfly(a0, a1, w1);  // stage lh: pairs at distance half
+      butterfly(a2, a3, w1);
+      butterfly(a0, a2, tw[pos * s2]);  // stage lh + 1: pairs at distance 2 half
+      butterfly(a1, a3, tw[(pos + half) * s2]);
+      buf[lds_pad(i0)] = a0;
+      buf[lds_pad(i1)] = a1;
+      buf[lds_pad(i2)] = a2;
+      buf[lds_pad(i3)] = a3;
+    }
+    __syncthreads();
+  }
+  if (lh < logn) {
     const int half = 1 << lh, stride = n >> (lh + 1);
     for (int b = threadIdx.x; b < n / 2; b += 256) {
       const int pos = b & (half - 1), grp = b >> lh;
       const int i = (grp << (lh + 1)) + pos, j = i + half;
-      const float2 w = tw[pos * stride], v = buf[j], u = buf[i];
-      const float2 t = make_float2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
-      buf[i] = make_float2(u.x + t.x, u.y + t.y);
-      buf[j] = make_float2(u.x - t.x, u.y - t.y);
+      float2 u = buf[lds_pad(i)], v = buf[lds_pad(j)];
+      butterfly(u, v, tw[pos * stride]);
+      buf[lds_pad(i)] = u;
+      buf[lds_pad(j)] = v;
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < n; i += 256) row[i] = buf[i];
+  for (int i = threadIdx.x; i < n; i += 256) row[i] = buf[lds_pad(i)];
 }
 
 // out = in^T, 32 x 32 tiles through LDS (32 x 8 threads).
@@ -325,16 +356,14 @@ hipError_t launch_pack(const float* s, int n, float2* za, float2* zb, float2* zc
   return hipGetLastError();
 }
 
-hipError_t launch_fft2(float2* z, float2* scratch, int n, int logn, bool inverse, hipStream_t st) {
-  const size_t lds = (size_t)n * sizeof(float2) + (size_t)(n / 2) * sizeof(float2);
+hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, hipStream_t st) {
+  const size_t lds = (size_t)(n + (n >> 5) + n / 2) * sizeof(float2);
   const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
-  for (int pass = 0; pass < 2; ++pass) {
-    float2* src = pass == 0 ? z : scratch;
-    float2* dst = pass == 0 ? scratch : z;
-    if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, src, n, logn);
-    else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, src, n, logn);
-    hipLaunchKernelGGL(k_transpose, tg, tb, 0, st, src, dst, n);
-  }
+  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, in, n, logn);
+  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, in, n, logn);
+  hipLaunchKernelGGL(k_transpose, tg, tb, 0, st, in, out, n);
+  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, out, n, logn);
+  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, out, n, logn);
   return hipGetLastError();
 }
 

@@ -159,8 +159,9 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 // Collision kernel.  A block owns a 64 x 8 tile of sites (256 threads, two rows
 // each).  phi and Q are staged with a halo of 2; mu and the nematic stress are
 // evaluated once per site on the tile plus a halo of 1 and shared through LDS;
-// the 18 population pulls are issued before the staging so their latency hides
-// behind it.  FIELDS = true evaluates the same velocities and densities and
+// a thread's staging loads and its 36 population pulls are all in flight before
+// its first LDS write, so the pulls' latency hides behind the staging and the
+// stress evaluation.  FIELDS = true evaluates the same velocities and densities and
 // writes them out instead of colliding (get_fields / diagnostics).
 // ---------------------------------------------------------------------------
 constexpr int CT_X = 64, CT_THREADS = 256;

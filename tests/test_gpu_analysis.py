@@ -108,3 +108,17 @@ def test_analysis_argument_errors(gpu):
     an = T.Analysis(16)
     with pytest.raises(T.TfanError):
         an.spectra(torch.zeros((7, 32, 32), device="cuda"))
+
+
+def test_observables_maximum_size(gpu):
+    """The largest grid the observables accept (4096 x 4096: 2,897 shells, 16.8 M
+    plaquettes).  The state is taken after 300 steps, when the random initial
+    director has relaxed: neighbouring angle differences near the +-pi/2 wrap
+    (where a one-ulp difference between two float32 atan2 implementations could
+    move a defect decision) are then confined to the defect cores."""
+    from paper_2511_00445_amd import Analysis
+    n = 4096
+    say(f"case: observables {n}x{n} after 300 steps (maximum size)")
+    an = Analysis(n)
+    assert an.shells == 2897
+    compare(an, solver_state(n, 300, seed=9), f"{n}x{n}")

@@ -500,8 +500,12 @@ template <int TH> __host__ __device__ inline int fused_tiles(int nx, int ny) {
   return ((nx + FF_X - 1) / FF_X) * ((ny + TH - 1) / TH);
 }
 
-// Row and column of entry c of a box w entries wide (c < 2^13, w >= 64): the
-// rounded product is at least 0.5 / w away from an integer, far above its error.
+// Row of entry c of a box w entries wide (c < 2^13, 64 <= w < 2^10): (c + 0.5) / w
+// is at least 0.5 / w away from an integer, while the product with the hardware
+// reciprocal (relative error below 2^-21 with the rounding of the product) is off by
+// less than 2^13 / 64 * 2^-21 = 6e-5 < 0.5 / w: the truncation is exact.  The
+// reciprocal is one instruction where an IEEE division takes about a dozen.
+__device__ __forceinline__ float box_inv(int w) { return __builtin_amdgcn_rcpf((float)w); }
 __device__ __forceinline__ int box_row(int c, float inv_w) { return (int)(((float)c + 0.5f) * inv_w); }
 
 // Frame offset of entry c (row cy) of a box whose rows are `gap` entries
@@ -592,7 +596,7 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
     // (1) mu on the phi box of halo r + 1
     {
       const int w = FF_X + 2 * (r + 1), cnt = w * (TH + 2 * (r + 1)), off = FF_HA - (r + 1);
-      const float inv = 1.f / (float)w;
+      const float inv = box_inv(w);
 #pragma unroll
       for (int k = 0; k < KM; ++k) {
         const int c = tid + k * NT;
@@ -604,7 +608,7 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
     }
     // (2) Beris-Edwards update on the Q box of halo s, into registers
     const int wq = FF_X + 2 * s, cq = wq * (TH + 2 * s), oq = FF_HB - s;
-    const float invq = 1.f / (float)wq;
+    const float invq = box_inv(wq);
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
       const int c = tid + k * NT;
@@ -620,7 +624,7 @@ __device__ __forceinline__ void fd_fused_tile(const DevParams& P, const DevState
     __syncthreads();
     // (3) Cahn-Hilliard update on the phi box of halo r, into registers
     const int wp = FF_X + 2 * r, cp = wp * (TH + 2 * r), op = FF_HA - r;
-    const float invp = 1.f / (float)wp;
+    const float invp = box_inv(wp);
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
       const int c = tid + k * NT;
@@ -781,7 +785,7 @@ __device__ __forceinline__ void phi_block_tile(const DevParams& P, const DevStat
     // (1) mu on the box of halo r + 1, two rows per strip
     {
       const int w = FF_X + 2 * (r + 1), cnt = w * ((TH + 2 * (r + 1)) / 2), o = H - (r + 1);
-      const float inv = 1.f / (float)w;
+      const float inv = box_inv(w);
 #pragma unroll
       for (int k = 0; k < B::KM; ++k) {
         const int c = tid + k * NT;
@@ -796,7 +800,7 @@ __device__ __forceinline__ void phi_block_tile(const DevParams& P, const DevStat
     __syncthreads();
     // (2) phi on the box of halo r, RP rows per strip, into registers
     const int w = FF_X + 2 * r, cnt = w * ((TH + 2 * r) / RP), o = H - r;
-    const float inv = 1.f / (float)w;
+    const float inv = box_inv(w);
 #pragma unroll
     for (int k = 0; k < B::KP; ++k) {
       const int c = tid + k * NT;
@@ -895,7 +899,7 @@ __device__ __forceinline__ void q_block_tile(const DevParams& P, const DevState&
   for (int m = 1; m <= S; ++m) {
     const int s = S - m;  // halo of the Q box of this sub-step
     const int w = FF_X + 2 * s, cnt = w * ((TH + 2 * s) / R), o = H - s;
-    const float inv = 1.f / (float)w;
+    const float inv = box_inv(w);
 #pragma unroll
     for (int k = 0; k < B::KQ; ++k) {
       const int c = tid + k * NT;

@@ -64,23 +64,38 @@ def measured_traffic(kernel: str):
     return None if k is None else float(k["bytes_per_launch"])
 
 
-def cpu_baseline(params, ic, budget_s: float):
+def cpu_baseline(params, ic, budget_s: float, single_core_s: float = 0.0):
     """The FP64 C oracle (oracle/coracle.c, OpenMP over rows), unchanged, on the same
-    grid: whole coupled steps until the time budget is used."""
-    from oracle.coracle import COracle, threads
-    o = COracle(params)
-    o.init_fields(ic["phi"], ic["qxx"], ic["qxy"])
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        o.step(1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el * (steps + 1) / steps > budget_s:
-            break
+    grid: whole coupled steps until the time budget is used, with every host thread;
+    with single_core_s > 0, the same again on one thread within that budget."""
+    from oracle.coracle import COracle, set_threads, threads
+
+    def timed(budget):
+        o = COracle(params)
+        o.init_fields(ic["phi"], ic["qxx"], ic["qxy"])
+        steps, t0 = 0, time.perf_counter()
+        while True:
+            o.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el * (steps + 1) / steps > budget:
+                return steps, el
+
     sites = params["nx"] * params["ny"]
-    return {"value": round(sites * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads(), "kind": "oracle",
-            "sample": f"{steps} coupled steps of the full {params['nx']}x{params['ny']} grid, FP64 C oracle "
-                      f"with {threads()} OpenMP threads, {el:.1f} s"}
+    steps, el = timed(budget_s)
+    out = {"value": round(sites * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads(), "kind": "oracle",
+           "sample": f"{steps} coupled steps of the full {params['nx']}x{params['ny']} grid, FP64 C oracle "
+                     f"with {threads()} OpenMP threads, {el:.1f} s"}
+    if single_core_s > 0:
+        n = threads()
+        set_threads(1)
+        try:
+            s1, e1 = timed(single_core_s)
+        finally:
+            set_threads(n)
+        out["single_core"] = {"value": round(sites * s1 / e1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"{s1} coupled steps of the same grid on one thread, {e1:.1f} s"}
+    return out
 
 
 def bench_sweep(args):
@@ -282,6 +297,8 @@ def main():
                     help="population storage (f16: binary16 deviations, float32 arithmetic)")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--single-core-budget", type=float, default=8.0,
+                    help="seconds of the oracle on one thread (0: skip)")
     ap.add_argument("--train-steps", type=int, default=12000,
                     help="surrogate_1024: Adam steps of the surrogate's training")
     ap.add_argument("--tuning", default="", metavar="C,F",
@@ -421,7 +438,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(p, ic, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(p, ic, args.cpu_budget, args.single_core_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -375,3 +375,14 @@ int oc_threads(void) {
   return 1;
 #endif
 }
+
+/* Number of OpenMP threads of later steps (n >= 1); timing only, the results do
+ * not depend on it (every row is computed by one thread, in the same order). */
+void oc_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

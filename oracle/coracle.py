@@ -33,12 +33,18 @@ def _load():
         lib.oc_step.argtypes = [ctypes.c_void_p, ctypes.c_int]
         lib.oc_fields.argtypes = [ctypes.c_void_p] + [dp] * 7
         lib.oc_threads.restype = ctypes.c_int
+        lib.oc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
 
 def threads() -> int:
     return int(_load().oc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of later steps (timing only: results do not depend on it)."""
+    _load().oc_set_threads(int(n))
 
 
 def _ptr(a):

@@ -24,3 +24,24 @@ def test_c_oracle_matches_numpy_oracle(nx, ny, steps, over):
     for k in fa:
         scale = max(np.abs(fa[k]).max(), 1e-30)
         assert np.abs(fa[k] - fb[k]).max() <= 1e-12 * scale, (k, np.abs(fa[k] - fb[k]).max(), scale)
+
+
+def test_c_oracle_results_do_not_depend_on_thread_count():
+    """The thread count (set for the single-core CPU baseline) changes only the
+    timing: every row is computed by one thread in a fixed order."""
+    from oracle.coracle import set_threads, threads
+    p = base_params(40, 24, zeta=0.02)
+    ic = initial_fields(40, 24, seed=3, phi_noise=0.2, S0=0.2)
+    out = []
+    n = threads()
+    try:
+        for t in (1, max(n, 2)):
+            set_threads(t)
+            o = COracle(p)
+            o.init_fields(ic["phi"], ic["qxx"], ic["qxy"])
+            o.step(3)
+            out.append(o.get_fields())
+    finally:
+        set_threads(n)
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k])

@@ -31,8 +31,10 @@ def run_bench(monkeypatch, capsys, argv):
 
 
 def test_bench_line_contract(gpu, monkeypatch, capsys):
-    print("case: bench.py --steps 40 --warmup 10 --cpu-budget 2", file=sys.__stderr__, flush=True)
-    b, d = run_bench(monkeypatch, capsys, ["--steps", "40", "--warmup", "10", "--cpu-budget", "2"])
+    print("case: bench.py --steps 40 --warmup 10 --cpu-budget 2 --single-core-budget 2", file=sys.__stderr__,
+          flush=True)
+    b, d = run_bench(monkeypatch, capsys, ["--steps", "40", "--warmup", "10", "--cpu-budget", "2",
+                                           "--single-core-budget", "2"])
     for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
               "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
         assert k in d, k
@@ -53,5 +55,6 @@ def test_bench_line_contract(gpu, monkeypatch, capsys):
     assert per_step_us <= d["ms_per_step"] * 1e3 * 1.05
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["unit"] == "MLUPS" and c["value"] > 0 and c["cores"] >= 1
+    assert c["single_core"]["cores"] == 1 and c["single_core"]["value"] > 0
     print(f"bench line: {d['value']} MLUPS, collision {r['avg_launch_us']} us ({r['frac']:.3f} of HBM), "
           f"cpu {c['value']} MLUPS", file=sys.__stderr__, flush=True)

@@ -90,6 +90,26 @@ def test_batch_members_match_single_runs(gpu, shape):
             assert np.array_equal(g[k], s[k]), (i, k)
 
 
+@pytest.mark.parametrize("shape", [(2, 165), (1, 4), (2, 162)])
+def test_batch_binary16_members_match_single_runs(gpu, shape):
+    """Binary16 population storage in the batched launches: each member bitwise
+    equal to its own single run."""
+    from paper_2511_00445_amd import Batch
+    say(f"case: binary16 batch vs single, shape {shape}")
+    ms = [dict(m, p=dict(m["p"], storage=1)) for m in _members()]
+    b = Batch([m["p"] for m in ms])
+    b.set_tuning(*shape)
+    for i, m in enumerate(ms):
+        b.init_fields(i, **m["ic"])
+    b.step(20)
+    for i, m in enumerate(ms):
+        g = b.get_fields(i)
+        s = single(m["p"], m["ic"], 20, shape).get_fields()
+        for k in g:
+            assert np.array_equal(g[k], s[k]), (i, k)
+    assert all(b.diagnostics(i)["status"] == 0 for i in range(len(ms)))
+
+
 def test_batch_member_reinit_and_oracle(gpu):
     from paper_2511_00445_amd import Batch
     say("case: batch re-init and oracle")

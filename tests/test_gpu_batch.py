@@ -9,7 +9,8 @@ from paper_2511_00445_amd.workloads import base_params, initial_fields
 
 pytestmark = pytest.mark.gpu
 # fd_shape 1, 2, 4: one launch per sub-step; 16, 32: all sub-steps in one launch;
-# 162, 163: blocks of 2 or 3 sub-steps per launch; 165: phi and Q in separate launches
+# 162, 163: blocks of 2 or 3 sub-steps per launch; 165: up to 5 sub-steps per launch, phi and Q
+# in separate thread blocks of one launch
 SHAPES = [(c, f) for c in (1, 2) for f in (1, 2, 4, 16, 32, 162, 163, 165)]
 
 

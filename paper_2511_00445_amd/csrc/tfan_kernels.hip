@@ -161,17 +161,27 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 }
 
 // ---------------------------------------------------------------------------
-// Collision kernel.  A block owns a 64 x 8 tile of sites (256 threads, two rows
-// each).  phi and Q are staged with a halo of 2; mu and the nematic stress are
+// Collision kernel.  A block owns a tile of CollideTile<PT>::X x (ROWS * SITES)
+// sites, SITES rows per thread.  phi and Q are staged with a halo of 2; mu and the nematic stress are
 // evaluated once per site on the tile plus a halo of 1 and shared through LDS;
 // a thread's staging loads and its 36 population pulls are all in flight before
 // its first LDS write, so the pulls' latency hides behind the staging and the
 // stress evaluation.  FIELDS = true evaluates the same velocities and densities and
 // writes them out instead of colliding (get_fields / diagnostics).
 // ---------------------------------------------------------------------------
-constexpr int CT_X = 64, CT_THREADS = 256;
-constexpr int CT_ROWS_PER_PASS = CT_THREADS / CT_X;  // 4 rows per pass of the block
-constexpr int PX = CT_X + 4, SX = CT_X + 2;          // phi/Q staging halo 2, mu/stress halo 1
+//
+// Tile shape per population type, measured at 2048^2 (two rows per thread).
+// Float32 pulls are non-temporal, so a cache line that x-shifted pulls share
+// across a tile edge is fetched again by the neighbouring tile: wide tiles have
+// fewer such edges (256 x 4 with 512 threads: 126 us; 128 x 8: 130 us; 64 x 8:
+// 137 us).  Binary16 pulls stay cached, and 64 x 8 with 256 threads is fastest
+// there (84 us; 128 x 4: 88 us; 256 x 4: 95 us).
+template <typename PT> struct CollideTile {
+  static constexpr bool WIDE = sizeof(PT) == 4;
+  static constexpr int X = WIDE ? 256 : 64, THREADS = WIDE ? 512 : 256;
+  static constexpr int ROWS = THREADS / X;          // rows per pass of the block
+  static constexpr int PX = X + 4, SX = X + 2;      // phi/Q staging halo 2, mu/stress halo 1
+};
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Launching 8 * ceil(tiles / 8) workgroups and giving XCD k the contiguous tile
@@ -234,14 +244,17 @@ __device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, floa
   return make_float2(q.x + h * ((sxx + P.Gamma * hxx) - 0.5f * ax), q.y + h * ((sxy + P.Gamma * hxy) - 0.5f * ay));
 }
 
-// Tiles of the collision kernel: CT_X x (4 * SITES) sites, SITES rows per thread.
-template <int SITES> __host__ __device__ inline int collide_tiles(int nx, int ny) {
-  return ((nx + CT_X - 1) / CT_X) * ((ny + CT_ROWS_PER_PASS * SITES - 1) / (CT_ROWS_PER_PASS * SITES));
+// Tiles of the collision kernel: X x (ROWS * SITES) sites, SITES rows per thread.
+template <typename PT, int SITES> __host__ __device__ inline int collide_tiles(int nx, int ny) {
+  using T = CollideTile<PT>;
+  return ((nx + T::X - 1) / T::X) * ((ny + T::ROWS * SITES - 1) / (T::ROWS * SITES));
 }
 
 template <bool FIELDS, typename PT, int CT_SITES>
 __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState& in, void* __restrict__ fout,
                                              float* __restrict__ uout, int tile) {
+  using T = CollideTile<PT>;
+  constexpr int CT_X = T::X, CT_THREADS = T::THREADS, CT_ROWS_PER_PASS = T::ROWS, PX = T::PX, SX = T::SX;
   constexpr int CT_Y = CT_ROWS_PER_PASS * CT_SITES, PY = CT_Y + 4, SY = CT_Y + 2;
   __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
   __shared__ float smu[SY][SX], sxx[SY][SX], syy[SY][SX], ssy[SY][SX], san[SY][SX];
@@ -345,9 +358,10 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
 }
 
 template <bool FIELDS, typename PT, int SITES>
-__global__ void __launch_bounds__(CT_THREADS) k_collide(DevParams P, DevState in, void* __restrict__ fout,
-                                                        float* __restrict__ uout) {
-  const int tile = xcd_tile(collide_tiles<SITES>(P.nx, P.ny));
+__global__ void __launch_bounds__(CollideTile<PT>::THREADS) k_collide(DevParams P, DevState in,
+                                                                      void* __restrict__ fout,
+                                                                      float* __restrict__ uout) {
+  const int tile = xcd_tile(collide_tiles<PT, SITES>(P.nx, P.ny));
   if (tile < 0) return;  // whole workgroup, before any barrier
   collide_tile<FIELDS, PT, SITES>(P, in, fout, uout, tile);
 }
@@ -363,7 +377,7 @@ __device__ __forceinline__ int batch_member(const int* __restrict__ first, int c
 }
 
 template <typename PT, int SITES>
-__global__ void __launch_bounds__(CT_THREADS) k_collide_batch(const BatchMember* __restrict__ mem,
+__global__ void __launch_bounds__(CollideTile<PT>::THREADS) k_collide_batch(const BatchMember* __restrict__ mem,
                                                               const int* __restrict__ first, int count,
                                                               int tiles, int cur) {
   const int tile = xcd_tile(tiles);
@@ -1165,22 +1179,21 @@ hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hip
   return hipGetLastError();
 }
 
-#define TFAN_POP_DISPATCH(KERNEL_F32, KERNEL_F16, ...)                        \
-  do {                                                                     \
-    if (P.pop16) hipLaunchKernelGGL(KERNEL_F16, __VA_ARGS__);                \
-    else hipLaunchKernelGGL(KERNEL_F32, __VA_ARGS__);                        \
-  } while (0)
+template <bool FIELDS, typename PT, int SITES>
+void launch_collide_tiles(const DevParams& P, DevState in, void* f_out, float* u_out, hipStream_t st) {
+  const dim3 grid(xcd_grid(collide_tiles<PT, SITES>(P.nx, P.ny)));
+  hipLaunchKernelGGL((k_collide<FIELDS, PT, SITES>), grid, dim3(CollideTile<PT>::THREADS), 0, st, P, in, f_out,
+                     u_out);
+}
 
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out, Tuning tn,
                           hipStream_t st) {
   if (tn.collide_rows == 1) {
-    const dim3 grid(xcd_grid(collide_tiles<1>(P.nx, P.ny)));
-    TFAN_POP_DISPATCH((k_collide<false, float, 1>), (k_collide<false, _Float16, 1>), grid, dim3(CT_THREADS), 0, st,
-                      P, in, f_out, u_out);
+    if (P.pop16) launch_collide_tiles<false, _Float16, 1>(P, in, f_out, u_out, st);
+    else launch_collide_tiles<false, float, 1>(P, in, f_out, u_out, st);
   } else {
-    const dim3 grid(xcd_grid(collide_tiles<2>(P.nx, P.ny)));
-    TFAN_POP_DISPATCH((k_collide<false, float, 2>), (k_collide<false, _Float16, 2>), grid, dim3(CT_THREADS), 0, st,
-                      P, in, f_out, u_out);
+    if (P.pop16) launch_collide_tiles<false, _Float16, 2>(P, in, f_out, u_out, st);
+    else launch_collide_tiles<false, float, 2>(P, in, f_out, u_out, st);
   }
   return hipGetLastError();
 }
@@ -1215,7 +1228,10 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
 }
 
 int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
-  if (collide) return tn.collide_rows == 1 ? collide_tiles<1>(P.nx, P.ny) : collide_tiles<2>(P.nx, P.ny);
+  if (collide) {
+    if (P.pop16) return tn.collide_rows == 1 ? collide_tiles<_Float16, 1>(P.nx, P.ny) : collide_tiles<_Float16, 2>(P.nx, P.ny);
+    return tn.collide_rows == 1 ? collide_tiles<float, 1>(P.nx, P.ny) : collide_tiles<float, 2>(P.nx, P.ny);
+  }
   if (fd_block(tn, P.n_sub) > 1) {
     if (fd_split(tn)) return fused_tiles<kSplitTile>(P.nx, P.ny);
     return fd_tile_rows(tn) == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
@@ -1225,13 +1241,13 @@ int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
 
 hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur, bool pop16,
                                 Tuning tn, hipStream_t st) {
-  const dim3 grid(xcd_grid(tiles));
+  const dim3 grid(xcd_grid(tiles)), b16(CollideTile<_Float16>::THREADS), b32(CollideTile<float>::THREADS);
   if (tn.collide_rows == 1) {
-    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 1>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
-    else hipLaunchKernelGGL((k_collide_batch<float, 1>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 1>), grid, b16, 0, st, mem, first, count, tiles, cur);
+    else hipLaunchKernelGGL((k_collide_batch<float, 1>), grid, b32, 0, st, mem, first, count, tiles, cur);
   } else {
-    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 2>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
-    else hipLaunchKernelGGL((k_collide_batch<float, 2>), grid, dim3(CT_THREADS), 0, st, mem, first, count, tiles, cur);
+    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 2>), grid, b16, 0, st, mem, first, count, tiles, cur);
+    else hipLaunchKernelGGL((k_collide_batch<float, 2>), grid, b32, 0, st, mem, first, count, tiles, cur);
   }
   return hipGetLastError();
 }
@@ -1264,9 +1280,8 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
 }
 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
-  const dim3 grid(xcd_grid(collide_tiles<2>(P.nx, P.ny)));
-  TFAN_POP_DISPATCH((k_collide<true, float, 2>), (k_collide<true, _Float16, 2>), grid, dim3(CT_THREADS), 0, st, P,
-                    in, nullptr, aux);
+  if (P.pop16) launch_collide_tiles<true, _Float16, 2>(P, in, nullptr, aux, st);
+  else launch_collide_tiles<true, float, 2>(P, in, nullptr, aux, st);
   return hipGetLastError();
 }
 

@@ -178,8 +178,9 @@ const char* tfan_kernel_name(int id);
  * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
  * 165: blocks of up to 5 sub-steps per launch on 64 x 32 tiles, the phi
  * (Cahn-Hilliard) and Q (Beris-Edwards) sub-steps in separate thread blocks.
- * Default (2, 165).  Results are bitwise identical for every shape; only the speed
- * differs.  Other values: TFAN_EINVAL. */
+ * Default (1, 165) below 2^21 sites, (2, 165) from there (a batch: (2, 165)).
+ * Results are bitwise identical for every shape; only the speed differs.  Other
+ * values: TFAN_EINVAL. */
 int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape);
 int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_shape);
 

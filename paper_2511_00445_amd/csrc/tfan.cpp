@@ -240,6 +240,7 @@ int tfan_create(const tfan_params* p, void* ws, size_t bytes, void* stream, tfan
   tfan_sim* s = new tfan_sim();
   s->p = *p;
   s->dp = dev_params(p);
+  s->tune = tfan::default_tuning(p->nx, p->ny);
   s->pop_bytes = p->storage == TFAN_STORAGE_F16 ? 2 : 4;
   s->stream = (hipStream_t)stream;
   (void)hipGetDevice(&s->device);

@@ -54,6 +54,16 @@ def test_fused_substeps_match_per_substep_launches(gpu, n_sub, nx, ny):
         assert np.array_equal(single(p, ic, 12, shape).get_state(), ref), shape
 
 
+def test_default_tuning_by_grid_size(gpu):
+    """One row of sites per collision thread below 2^21 sites, two from there."""
+    from paper_2511_00445_amd import Sim
+    say("case: default launch shape by grid size")
+    for (nx, ny), rows in (((64, 64), 1), ((1024, 1024), 1), ((2048, 1024), 2), ((2048, 2048), 2)):
+        s = Sim(base_params(nx, ny))
+        assert s.get_tuning() == (rows, 165), (nx, ny, s.get_tuning())
+        s.close()
+
+
 def test_autotune_keeps_state(gpu):
     from paper_2511_00445_amd import Sim
     say("case: autotune")

@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+ANALYSIS_BYTES_PER_SITE = 52 + 5 * 2 * 16 + 48 + 24 + 8  # one observables snapshot (bench_analysis)
 # fp32 vector peak without packed fp32 instructions (the build disables them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -222,7 +223,8 @@ def bench_surrogate(args):
 
 def bench_analysis(args):
     """On-device observables of one 2048x2048 snapshot (spectra + L, correlations,
-    defects) against the FP64 numpy oracle on the host, same float32 state."""
+    defects in one tfan_analysis_all call) against the FP64 numpy oracle on the host,
+    same float32 state."""
     import numpy as np
     import torch
     from paper_2511_00445_amd import Analysis, Sim
@@ -239,9 +241,7 @@ def bench_analysis(args):
     an = Analysis(n)
 
     def snapshot():
-        an.spectra(x)
-        an.correlations(x)
-        an.defects(x)
+        an.all(x)
 
     snapshot()  # warm-up
     reps = max(1, args.steps // 200)
@@ -260,8 +260,12 @@ def bench_analysis(args):
             fn()
         torch.cuda.synchronize()
         parts[name] = round((time.perf_counter() - t1) / reps * 1e3, 3)
-    # algorithmic bytes of one snapshot: the state read once by each of the three calls
-    alg = 3 * 7 * 4 * n * n
+    # algorithmic bytes of one snapshot, per site: packing (7 state planes read, 3
+    # complex fields written: 52 B), five 2D FFTs at two read+write passes of
+    # complex64 each (the least an FFT of an array larger than the chip's caches
+    # moves: 160 B), power spectra (24 B read, 24 B written), shell sums (pE, pS
+    # and two complex correlation maps read: 24 B), defect count (Qxx, Qxy: 8 B)
+    alg = ANALYSIS_BYTES_PER_SITE * n * n
     achieved = alg / per / 1e9
     out = {"metric": "analysed snapshots per second (spectra + L, correlations, defects)",
            "value": round(1.0 / per, 2), "unit": "snapshots/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
@@ -270,7 +274,7 @@ def bench_analysis(args):
            "config": {"workload": f"analysis_2048: one 2048x2048 snapshot of large_2048 after {args.warmup} steps",
                       "nx": n, "ny": n, "parallelism": "single GPU"},
            "ms_per_call": parts,
-           "roofline": {"bound": "hbm", "kernel": "whole snapshot (FFT passes, shell sums, defects)",
+           "roofline": {"bound": "hbm", "kernel": "whole snapshot (packing, FFT passes, powers, shell sums, defects)",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                         "alg_bytes_per_launch": alg, "avg_launch_us": round(per * 1e6, 1)}}

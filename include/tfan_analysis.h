@@ -70,6 +70,15 @@ int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, d
 /* Numbers of +1/2 and -1/2 defects. */
 int tfan_analysis_defects(tfan_analysis* a, const float* state, int64_t* plus, int64_t* minus);
 
+/* Everything above for one state in one call, the three forward transforms
+ * computed once: the same values as tfan_analysis_spectra, _correlations and
+ * _defects on that state (bitwise: the same kernels).  The shell counts of the
+ * spectra and of the correlations are the same numbers (wavevectors and
+ * minimum-image displacements fall in the same shells) and are returned once.
+ * Array arguments as above, any may be NULL; plus and minus may be NULL. */
+int tfan_analysis_all(tfan_analysis* a, const float* state, double* E, double* W, double* S, double* L,
+                      double* Cuu, double* Cww, double* CQQ, double* count, int64_t* plus, int64_t* minus);
+
 int tfan_analysis_sync(tfan_analysis* a);
 void tfan_analysis_destroy(tfan_analysis* a);
 const char* tfan_analysis_last_error(const tfan_analysis* a);

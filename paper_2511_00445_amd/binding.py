@@ -557,6 +557,20 @@ class Analysis:
                                                         _ptr(out["ww"]), _ptr(out["QQ"]), _ptr(out["count"])))
         return out
 
+    def all(self, x) -> dict:
+        """Spectra, L, correlations and defect counts of one state in one call (the
+        forward transforms computed once); keys as spectra() and correlations(),
+        plus "defects" = (plus, minus)."""
+        out = {k: np.empty(self.shells) for k in ("E", "W", "S", "uu", "ww", "QQ", "count")}
+        L, p, m = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tfan_analysis_all(self._handle, self._state(x), _ptr(out["E"]), _ptr(out["W"]),
+                                               _ptr(out["S"]), ctypes.byref(L), _ptr(out["uu"]), _ptr(out["ww"]),
+                                               _ptr(out["QQ"]), _ptr(out["count"]), ctypes.byref(p),
+                                               ctypes.byref(m)))
+        out["L"] = L.value
+        out["defects"] = (p.value, m.value)
+        return out
+
     def overlaps(self, x0, x1) -> np.ndarray:
         out = np.empty(6)
         self._check(self.lib.tfan_analysis_overlaps(self._handle, self._state(x0), self._state(x1), _ptr(out)))

@@ -101,6 +101,51 @@ int transforms(tfan_analysis* a, const float* s) {
   return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "transforms");
 }
 
+// Shell sums of the spectra and L from the transforms; results copied out
+// (stream-ordered, before any later kernel reuses the output buffer).
+int spectra_from_transforms(tfan_analysis* a, double* E, double* W, double* S, double* count, double* L) {
+  const int ns = a->ns;
+  double* out = a->at<double>(a->p.out);
+  hipError_t e = tana::launch_shells(a->at<float>(a->p.pE), a->at<float>(a->p.pS), nullptr, 1, a->n, ns, false,
+                                     a->at<double>(a->p.partial), a->at<int>(a->p.pcount), out, a->stream);
+  if (e == hipSuccess) e = tana::launch_finish_spectra(out, a->n, ns, a->stream);
+  if (e != hipSuccess) return hip_fail(a, e, "spectra");
+  int rc;
+  if ((rc = copy_out(a, E, out, ns)) || (rc = copy_out(a, S, out + ns, ns)) || (rc = copy_out(a, W, out + 2 * ns, ns)) ||
+      (rc = copy_out(a, count, out + 3 * ns, ns)) || (rc = copy_out(a, L, out + 4 * ns, 1)))
+    return rc;
+  return TFAN_OK;
+}
+
+// Inverse transforms of the (transposed) powers, which come out in natural
+// layout, and their shell means; results copied out.
+int correlations_from_transforms(tfan_analysis* a, double* Cuu, double* Cww, double* CQQ, double* count) {
+  float2* c0 = a->at<float2>(a->p.z[2]);
+  float2* c1 = a->at<float2>(a->p.scratch);
+  hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->stream);
+  const int ns = a->ns;
+  double* out = a->at<double>(a->p.out);
+  if (e == hipSuccess)
+    e = tana::launch_shells(reinterpret_cast<const float*>(c0), reinterpret_cast<const float*>(c0) + 1,
+                            reinterpret_cast<const float*>(c1), 2, a->n, ns, true, a->at<double>(a->p.partial),
+                            a->at<int>(a->p.pcount), out, a->stream);
+  if (e != hipSuccess) return hip_fail(a, e, "correlations");
+  int rc;
+  if ((rc = copy_out(a, Cuu, out, ns)) || (rc = copy_out(a, Cww, out + ns, ns)) ||
+      (rc = copy_out(a, CQQ, out + 2 * ns, ns)) || (rc = copy_out(a, count, out + 3 * ns, ns)))
+    return rc;
+  return TFAN_OK;
+}
+
+// Defect counts into the host pair (stream-ordered copy; the caller synchronises).
+int defects_enqueue(tfan_analysis* a, const float* s, double* host2) {
+  double* d = a->at<double>(a->p.dout);
+  hipError_t e = tana::launch_defects(s, a->n, a->at<double>(a->p.dpart), d, a->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host2, d, 16, hipMemcpyDeviceToHost, a->stream);
+  return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "defects");
+}
+
 }  // namespace
 
 extern "C" {
@@ -140,16 +185,8 @@ int tfan_analysis_spectra(tfan_analysis* a, const float* s, double* E, double* W
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
   int rc = transforms(a, s);
   if (rc) return rc;
-  const int ns = a->ns;
-  double* out = a->at<double>(a->p.out);
-  hipError_t e = tana::launch_shells(a->at<float>(a->p.pE), a->at<float>(a->p.pS), nullptr, 1, a->n, ns, false,
-                                     a->at<double>(a->p.partial), a->at<int>(a->p.pcount), out, a->stream);
-  if (e == hipSuccess) e = tana::launch_finish_spectra(out, a->n, ns, a->stream);
-  if (e != hipSuccess) return hip_fail(a, e, "spectra");
-  if ((rc = copy_out(a, E, out, ns)) || (rc = copy_out(a, S, out + ns, ns)) || (rc = copy_out(a, W, out + 2 * ns, ns)) ||
-      (rc = copy_out(a, count, out + 3 * ns, ns)) || (rc = copy_out(a, L, out + 4 * ns, 1)))
-    return rc;
-  return finish(a);
+  rc = spectra_from_transforms(a, E, W, S, count, L);
+  return rc ? rc : finish(a);
 }
 
 int tfan_analysis_correlations(tfan_analysis* a, const float* s, double* Cuu, double* Cww, double* CQQ,
@@ -158,22 +195,8 @@ int tfan_analysis_correlations(tfan_analysis* a, const float* s, double* Cuu, do
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
   int rc = transforms(a, s);
   if (rc) return rc;
-  // inverse transforms of the (transposed) powers come out in natural layout
-  float2* c0 = a->at<float2>(a->p.z[2]);
-  float2* c1 = a->at<float2>(a->p.scratch);
-  hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->stream);
-  const int ns = a->ns;
-  double* out = a->at<double>(a->p.out);
-  if (e == hipSuccess)
-    e = tana::launch_shells(reinterpret_cast<const float*>(c0), reinterpret_cast<const float*>(c0) + 1,
-                            reinterpret_cast<const float*>(c1), 2, a->n, ns, true, a->at<double>(a->p.partial),
-                            a->at<int>(a->p.pcount), out, a->stream);
-  if (e != hipSuccess) return hip_fail(a, e, "correlations");
-  if ((rc = copy_out(a, Cuu, out, ns)) || (rc = copy_out(a, Cww, out + ns, ns)) ||
-      (rc = copy_out(a, CQQ, out + 2 * ns, ns)) || (rc = copy_out(a, count, out + 3 * ns, ns)))
-    return rc;
-  return finish(a);
+  rc = correlations_from_transforms(a, Cuu, Cww, CQQ, count);
+  return rc ? rc : finish(a);
 }
 
 int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, double* out) {
@@ -189,14 +212,28 @@ int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, d
 int tfan_analysis_defects(tfan_analysis* a, const float* s, int64_t* plus, int64_t* minus) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s || !plus || !minus) return fail(a, TFAN_EINVAL, "NULL argument");
-  double* d = a->at<double>(a->p.dout);
-  hipError_t e = tana::launch_defects(s, a->n, a->at<double>(a->p.dpart), d, a->stream);
   double h[2] = {0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(h, d, 16, hipMemcpyDeviceToHost, a->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(a->stream);
-  if (e != hipSuccess) return hip_fail(a, e, "defects");
+  int rc = defects_enqueue(a, s, h);
+  if (rc) return rc;
+  if ((rc = finish(a))) return rc;
   *plus = (int64_t)h[0];
   *minus = (int64_t)h[1];
+  return TFAN_OK;
+}
+
+int tfan_analysis_all(tfan_analysis* a, const float* s, double* E, double* W, double* S, double* L, double* Cuu,
+                      double* Cww, double* CQQ, double* count, int64_t* plus, int64_t* minus) {
+  if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
+  int rc = transforms(a, s);
+  if (rc) return rc;
+  if ((rc = spectra_from_transforms(a, E, W, S, count, L))) return rc;
+  if ((rc = correlations_from_transforms(a, Cuu, Cww, CQQ, nullptr))) return rc;
+  double h[2] = {0, 0};
+  if ((rc = defects_enqueue(a, s, h))) return rc;
+  if ((rc = finish(a))) return rc;
+  if (plus) *plus = (int64_t)h[0];
+  if (minus) *minus = (int64_t)h[1];
   return TFAN_OK;
 }
 

@@ -32,6 +32,10 @@ def test_roofline_constants():
     assert b.ALG_BYTES["step"] == 2 * 9 * 4 * 2 + 3 * 4 * 2
     assert b.ALG_BYTES["collide"] == 2 * 9 * 4 * 2 + 3 * 4 + 4 * 4
     assert b.ALG_BYTES["substeps"] == 3 * 4 + 4 * 4 + 3 * 4
+    # observables snapshot: packing 7 x 4 read + 3 x 8 written, five 2D FFTs of two
+    # read+write passes over complex64, powers 3 x 8 read + 2 x 4 + 2 x 8 written,
+    # shell sums 2 x 4 + 2 x 8 read, defects 2 x 4 read
+    assert b.ANALYSIS_BYTES_PER_SITE == (7 * 4 + 3 * 8) + 5 * 2 * 2 * 8 + (3 * 8 + 2 * 4 + 2 * 8) + (2 * 4 + 2 * 8) + 2 * 4
 
 
 def test_traffic_record_matches_sources_or_is_ignored():

@@ -122,3 +122,23 @@ def test_observables_maximum_size(gpu):
     an = Analysis(n)
     assert an.shells == 2897
     compare(an, solver_state(n, 300, seed=9), f"{n}x{n}")
+
+
+@pytest.mark.parametrize("n,steps", [(64, 20), (512, 30)])
+def test_all_in_one_call_equals_separate_calls(gpu, n, steps):
+    """tfan_analysis_all shares the forward transforms: its results equal the
+    separate calls bitwise, and the oracle to the bounds above."""
+    from paper_2511_00445_amd import Analysis
+    say(f"case: combined observables call {n}x{n}")
+    an = Analysis(n)
+    x = solver_state(n, steps, seed=60 + n)
+    a, sp, c, d = an.all(x), an.spectra(x), an.correlations(x), an.defects(x)
+    for k in ("E", "W", "S", "count"):
+        np.testing.assert_array_equal(a[k], sp[k])
+    assert a["L"] == sp["L"]
+    for k in ("uu", "ww", "QQ"):
+        np.testing.assert_array_equal(a[k], c[k])
+    np.testing.assert_array_equal(a["count"], c["count"])
+    assert a["defects"] == d
+    ref = A.spectra(x.cpu().numpy().astype(np.float64))
+    assert np.max(np.abs(a["E"] - ref["E"])) <= 1e-5 * np.max(np.abs(ref["E"]))

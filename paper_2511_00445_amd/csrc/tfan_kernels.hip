@@ -18,10 +18,11 @@ constexpr float WT[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
 
 // Population storage: float32, or IEEE binary16 of the same shifted values
 // (arithmetic is float32 either way; the conversion rounds to nearest even).
-// Float32 populations are pulled with a non-temporal hint as well: each value is
-// read by one site, and keeping the 144 B/site stream out of the caches leaves
-// phi, Q and the velocities resident (measured at 2048^2: collision and sub-steps
-// both 3.5% shorter).  For binary16 the hint made the collision 2.5% longer.
+// Populations are pulled with a non-temporal hint as well: each value is read by
+// one site, and keeping the population stream out of the caches leaves phi, Q
+// and the velocities resident (measured at 2048^2, float32: collision and
+// sub-steps both 3.5% shorter; binary16 with both fluids in one 4-byte word:
+// collision 3% shorter).
 template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, size_t i) {
   if constexpr (sizeof(PT) == 4) return __builtin_nontemporal_load(static_cast<const float*>(f) + i);
   else return (float)static_cast<const PT*>(f)[i];
@@ -31,6 +32,37 @@ template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, si
 // frozen velocities resident for the sub-step passes that follow.
 template <typename PT> __device__ __forceinline__ void pop_st(void* f, size_t i, float v) {
   __builtin_nontemporal_store((PT)v, static_cast<PT*>(f) + i);
+}
+// Element (fluid fl, direction i, site) of one population set: float32 in planes
+// [2][9][n]; binary16 with the two fluids of one direction and site side by side
+// ([9][n][2]), so that a pull or a store of both fluids is one 4-byte access
+// (half the memory instructions of two 2-byte ones: collision 85 -> 82 us).
+template <typename PT> __device__ __forceinline__ size_t pop_index(int fl, int i, size_t n, size_t site) {
+  if constexpr (sizeof(PT) == 4) return (size_t)(9 * fl + i) * n + site;
+  else return (((size_t)i * n + site) << 1) + (size_t)fl;
+}
+// Both fluids' populations of direction i at a site.
+template <typename PT>
+__device__ __forceinline__ void pop_ld2(const void* f, int i, size_t n, size_t site, float& a, float& p) {
+  if constexpr (sizeof(PT) == 4) {
+    a = pop_ld<float>(f, pop_index<float>(0, i, n, site));
+    p = pop_ld<float>(f, pop_index<float>(1, i, n, site));
+  } else {
+    const unsigned v = __builtin_nontemporal_load(static_cast<const unsigned*>(f) + (size_t)i * n + site);
+    a = (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
+    p = (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
+  }
+}
+template <typename PT>
+__device__ __forceinline__ void pop_st2(void* f, int i, size_t n, size_t site, float a, float p) {
+  if constexpr (sizeof(PT) == 4) {
+    pop_st<float>(f, pop_index<float>(0, i, n, site), a);
+    pop_st<float>(f, pop_index<float>(1, i, n, site), p);
+  } else {
+    const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)a);
+    const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)p);
+    __builtin_nontemporal_store(lo | (hi << 16), static_cast<unsigned*>(f) + (size_t)i * n + site);
+  }
 }
 
 // Periodic index for offsets |d| <= n.
@@ -174,11 +206,12 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 // Float32 pulls are non-temporal, so a cache line that x-shifted pulls share
 // across a tile edge is fetched again by the neighbouring tile: wide tiles have
 // fewer such edges (256 x 4 with 512 threads: 126 us; 128 x 8: 130 us; 64 x 8:
-// 137 us).  Binary16 pulls stay cached, and 64 x 8 with 256 threads is fastest
-// there (84 us; 128 x 4: 88 us; 256 x 4: 95 us).
+// 137 us).  Binary16 (one 4-byte word per direction and site, non-temporal):
+// 128 x 4 with 256 threads is fastest there (77 us; 64 x 8: 79 us; 256 x 4 with
+// 512 threads: 85 us).
 template <typename PT> struct CollideTile {
-  static constexpr bool WIDE = sizeof(PT) == 4;
-  static constexpr int X = WIDE ? 256 : 64, THREADS = WIDE ? 512 : 256;
+  static constexpr bool F32 = sizeof(PT) == 4;
+  static constexpr int X = F32 ? 256 : 128, THREADS = F32 ? 512 : 256;
   static constexpr int ROWS = THREADS / X;          // rows per pass of the block
   static constexpr int PX = X + 4, SX = X + 2;      // phi/Q staging halo 2, mu/stress halo 1
 };
@@ -297,8 +330,7 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
     for (int i = 0; i < 9; ++i) {
       const int sx = (CX[i] == 0) ? xc : (CX[i] > 0 ? xm1 : xp1);
       const int sy = (CY[i] == 0) ? r0 : (CY[i] > 0 ? rm1 : rp1);
-      fa[s][i] = pop_ld<PT>(in.f, (size_t)i * n + sy + sx);
-      fp[s][i] = pop_ld<PT>(in.f, (size_t)(9 + i) * n + sy + sx);
+      pop_ld2<PT>(in.f, i, (size_t)n, (size_t)(sy + sx), fa[s][i], fp[s][i]);
     }
   }
 #pragma unroll
@@ -348,8 +380,7 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        pop_st<PT>(fout, (size_t)i * n + idx, fa[s][i]);
-        pop_st<PT>(fout, (size_t)(9 + i) * n + idx, fp[s][i]);
+        pop_st2<PT>(fout, i, (size_t)n, (size_t)idx, fa[s][i], fp[s][i]);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) uout[c * n + idx] = uo[c];
@@ -1041,7 +1072,7 @@ __global__ void __launch_bounds__(256) k_init(DevParams P, const float* __restri
     for (int s = 0; s < 2; ++s) {
       const float ux = aux[(2 * s) * n + src], uy = aux[(2 * s + 1) * n + src];
       const float cu = (float)CX[i] * ux + (float)CY[i] * uy;
-      pop_st<PT>(f, (size_t)(9 * s + i) * n + idx,
+      pop_st<PT>(f, pop_index<PT>(s, i, (size_t)n, (size_t)idx),
                  WT[i] * P.rho0 * (cu * (3.f + 4.5f * cu) - 1.5f * (ux * ux + uy * uy)));
     }
   }
@@ -1138,7 +1169,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DevParams P, DevState in,
     acc[D_S] += sqrt(q1 * q1 + q2 * q2);
     int bad = is_bad(in.phi[idx]) + is_bad(qx[idx]) + is_bad(qy[idx]);
 #pragma unroll
-    for (int i = 0; i < 18; ++i) bad += is_bad(pop_ld<PT>(in.f, (size_t)i * n + idx));
+    for (int i = 0; i < 18; ++i) bad += is_bad(pop_ld<PT>(in.f, pop_index<PT>(i / 9, i % 9, (size_t)n, (size_t)idx)));
     acc[D_NONFINITE] += (double)bad;
   }
   block_reduce_store(acc, partials + (size_t)blockIdx.x * kDiagSlots);

@@ -21,8 +21,7 @@ constexpr float WT[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
 // Populations are pulled with a non-temporal hint as well: each value is read by
 // one site, and keeping the population stream out of the caches leaves phi, Q
 // and the velocities resident (measured at 2048^2, float32: collision and
-// sub-steps both 3.5% shorter; binary16 with both fluids in one 4-byte word:
-// collision 3% shorter).
+// sub-steps both 3.5% shorter; binary16: collision 3% shorter).
 template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, size_t i) {
   if constexpr (sizeof(PT) == 4) return __builtin_nontemporal_load(static_cast<const float*>(f) + i);
   else return (float)static_cast<const PT*>(f)[i];
@@ -33,20 +32,22 @@ template <typename PT> __device__ __forceinline__ float pop_ld(const void* f, si
 template <typename PT> __device__ __forceinline__ void pop_st(void* f, size_t i, float v) {
   __builtin_nontemporal_store((PT)v, static_cast<PT*>(f) + i);
 }
-// Element (fluid fl, direction i, site) of one population set: float32 in planes
-// [2][9][n]; binary16 with the two fluids of one direction and site side by side
-// ([9][n][2]), so that a pull or a store of both fluids is one 4-byte access
-// (half the memory instructions of two 2-byte ones: collision 85 -> 82 us).
+// Element (fluid fl, direction i, site) of one population set, [9][n][2]: the two
+// fluids of one direction and site side by side, so that a pull or a store of
+// both fluids is one 8-byte (float32) or 4-byte (binary16) access, half the
+// memory instructions of separate planes (collision at 2048^2: float32 127 ->
+// 122 us, binary16 85 -> 82 us).
 template <typename PT> __device__ __forceinline__ size_t pop_index(int fl, int i, size_t n, size_t site) {
-  if constexpr (sizeof(PT) == 4) return (size_t)(9 * fl + i) * n + site;
-  else return (((size_t)i * n + site) << 1) + (size_t)fl;
+  return (((size_t)i * n + site) << 1) + (size_t)fl;
 }
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 // Both fluids' populations of direction i at a site.
 template <typename PT>
 __device__ __forceinline__ void pop_ld2(const void* f, int i, size_t n, size_t site, float& a, float& p) {
   if constexpr (sizeof(PT) == 4) {
-    a = pop_ld<float>(f, pop_index<float>(0, i, n, site));
-    p = pop_ld<float>(f, pop_index<float>(1, i, n, site));
+    const f32x2_t v = __builtin_nontemporal_load(static_cast<const f32x2_t*>(f) + (size_t)i * n + site);
+    a = v.x;
+    p = v.y;
   } else {
     const unsigned v = __builtin_nontemporal_load(static_cast<const unsigned*>(f) + (size_t)i * n + site);
     a = (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
@@ -56,8 +57,10 @@ __device__ __forceinline__ void pop_ld2(const void* f, int i, size_t n, size_t s
 template <typename PT>
 __device__ __forceinline__ void pop_st2(void* f, int i, size_t n, size_t site, float a, float p) {
   if constexpr (sizeof(PT) == 4) {
-    pop_st<float>(f, pop_index<float>(0, i, n, site), a);
-    pop_st<float>(f, pop_index<float>(1, i, n, site), p);
+    f32x2_t v;
+    v.x = a;
+    v.y = p;
+    __builtin_nontemporal_store(v, static_cast<f32x2_t*>(f) + (size_t)i * n + site);
   } else {
     const unsigned lo = __builtin_bit_cast(unsigned short, (_Float16)a);
     const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)p);
@@ -203,12 +206,11 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 // ---------------------------------------------------------------------------
 //
 // Tile shape per population type, measured at 2048^2 (two rows per thread).
-// Float32 pulls are non-temporal, so a cache line that x-shifted pulls share
-// across a tile edge is fetched again by the neighbouring tile: wide tiles have
-// fewer such edges (256 x 4 with 512 threads: 126 us; 128 x 8: 130 us; 64 x 8:
-// 137 us).  Binary16 (one 4-byte word per direction and site, non-temporal):
-// 128 x 4 with 256 threads is fastest there (77 us; 64 x 8: 79 us; 256 x 4 with
-// 512 threads: 85 us).
+// Pulls are non-temporal, so a cache line that x-shifted pulls share across a
+// tile edge is fetched again by the neighbouring tile: float32 wants wide tiles
+// (256 x 4 with 512 threads: 122 us; 128 x 4 with 256: 123 us; before the paired
+// fluids, 64 x 8: 137 us).  Binary16: 128 x 4 with 256 threads (77 us; 64 x 8:
+// 79 us; 256 x 4 with 512 threads: 85 us).
 template <typename PT> struct CollideTile {
   static constexpr bool F32 = sizeof(PT) == 4;
   static constexpr int X = F32 ? 256 : 128, THREADS = F32 ? 512 : 256;

@@ -176,7 +176,7 @@ const char* tfan_kernel_name(int id);
  * 16, 32: all n_sub sub-steps of a step in one launch on 64 x fd_shape tiles
  * (temporal blocking; for n_sub > 5 the 4-row per-sub-step launch runs);
  * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
- * 165: blocks of up to 5 sub-steps per launch on 64 x 32 tiles, the phi
+ * 165: blocks of up to 5 sub-steps per launch on 64 x 40 tiles, the phi
  * (Cahn-Hilliard) and Q (Beris-Edwards) sub-steps in separate thread blocks.
  * Default (1, 165) below 2^21 sites, (2, 165) from there (a batch: (2, 165)).
  * Results are bitwise identical for every shape; only the speed differs.  Other

@@ -48,7 +48,7 @@ struct DevState {
 // {162, 163}: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
 // 165: blocks of up to kFusedMaxSub sub-steps on 64 x kSplitTile tiles, with
 // separate thread blocks for phi and Q in one launch.
-constexpr int kFusedMaxSub = 5, kSplitTile = 32;
+constexpr int kFusedMaxSub = 5, kSplitTile = 40;
 struct Tuning {
   int collide_rows = 2;
   int fd_shape = 165;

@@ -747,8 +747,10 @@ __global__ void __launch_bounds__((Fused<TH, MS>::NT)) k_fd_fused_batch(const Ba
 // block holds only its own frames in LDS.  Threads update strips of R vertically
 // consecutive sites of one column: the north/south stencil values of a strip are
 // read once from LDS and shared through registers.  Site arithmetic is that of
-// fd_tile, term for term.  On 64 x 32 tiles with five sub-steps the phi block
-// recomputes 1.5x (mu) and 1.4x (phi) the sites of its tile, the Q block 1.2x.
+// fd_tile, term for term.  On 64 x 40 tiles with five sub-steps the phi block
+// recomputes 1.46x (mu) and 1.36x (phi) the sites of its tile, the Q block 1.17x
+// (64 x 32: 1.53x, 1.42x, 1.20x and 3% longer; 64 x 40 is the tallest tile whose
+// phi frames, 81 KB, still let two blocks share a compute unit's 160 KB of LDS).
 // ---------------------------------------------------------------------------
 template <int TH, int MS> struct PhiBlock {
   static constexpr int H = 2 * MS;                           // frame halo

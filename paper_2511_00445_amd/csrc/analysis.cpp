@@ -27,7 +27,7 @@ int shell_of(long long m2) {
 }
 
 struct Plan {
-  size_t z[3], scratch, w[2], pE, pS, partial, pcount, out, red, dpart, dout, total;
+  size_t z[3], scratch, w[2], pE, pS, partial, pcount, out, red, dpart, dout, tw, total;
 };
 
 Plan plan(int n, int ns) {
@@ -51,6 +51,7 @@ Plan plan(int n, int ns) {
   p.red = take((size_t)tana::reduce_blocks(n) * 6 * 8 + 64);
   p.dpart = take((size_t)tana::reduce_blocks(n) * 2 * 8);
   p.dout = take(2 * 8);
+  p.tw = take((size_t)(n / 2) * 8);
   p.total = o;
   return p;
 }
@@ -64,6 +65,7 @@ struct tfan_analysis {
   Plan p{};
   std::string err;
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+  const float2* twiddles() const { return at<float2>(p.tw); }
 };
 
 namespace {
@@ -92,9 +94,9 @@ int transforms(tfan_analysis* a, const float* s) {
   float2* z[3] = {a->at<float2>(a->p.z[0]), a->at<float2>(a->p.z[1]), a->at<float2>(a->p.z[2])};
   float2* scratch = a->at<float2>(a->p.scratch);
   hipError_t e = tana::launch_pack(s, a->n, z[0], z[1], z[2], a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2t(z[0], scratch, a->n, a->logn, false, a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2t(z[1], z[0], a->n, a->logn, false, a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2t(z[2], z[1], a->n, a->logn, false, a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[0], scratch, a->n, a->logn, false, a->twiddles(), a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[1], z[0], a->n, a->logn, false, a->twiddles(), a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(z[2], z[1], a->n, a->logn, false, a->twiddles(), a->stream);
   if (e == hipSuccess)
     e = tana::launch_power(scratch, z[0], z[1], a->n, a->at<float>(a->p.pE), a->at<float>(a->p.pS),
                            a->at<float2>(a->p.w[0]), a->at<float2>(a->p.w[1]), a->stream);
@@ -122,8 +124,8 @@ int spectra_from_transforms(tfan_analysis* a, double* E, double* W, double* S, d
 int correlations_from_transforms(tfan_analysis* a, double* Cuu, double* Cww, double* CQQ, double* count) {
   float2* c0 = a->at<float2>(a->p.z[2]);
   float2* c1 = a->at<float2>(a->p.scratch);
-  hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->stream);
-  if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->stream);
+  hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->twiddles(), a->stream);
+  if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->twiddles(), a->stream);
   const int ns = a->ns;
   double* out = a->at<double>(a->p.out);
   if (e == hipSuccess)
@@ -175,6 +177,12 @@ int tfan_analysis_create(int32_t n, void* ws, size_t bytes, void* stream, tfan_a
   a->stream = (hipStream_t)stream;
   a->base = (char*)ws;
   a->p = p;
+  // the FFT twiddle table, enqueued on the handle's stream ahead of every later call
+  hipError_t e = tana::launch_twiddles(a->at<float2>(p.tw), n, a->stream);
+  if (e != hipSuccess) {
+    delete a;
+    return fail(nullptr, TFAN_EHIP, std::string("twiddle table: ") + hipGetErrorName(e));
+  }
   *out = a;
   return TFAN_OK;
 }

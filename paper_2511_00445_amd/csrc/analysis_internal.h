@@ -13,7 +13,9 @@ hipError_t launch_pack(const float* state, int n, float2* za, float2* zb, float2
 // are symmetric in the two axes, and the transposed-layout inverse of a
 // transposed array is the natural-layout inverse, so the second transpose of
 // each transform is never needed.
-hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, hipStream_t st);
+hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, const float2* tw, hipStream_t st);
+// Table of the n / 2 forward twiddles exp(-2 pi i k / n) used by launch_fft2t.
+hipError_t launch_twiddles(float2* tw, int n, hipStream_t st);
 // Power spectra and the inverse-transform inputs of the correlations (see k_power).
 hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, int n, float* pE, float* pS,
                         float2* w0, float2* w1, hipStream_t st);

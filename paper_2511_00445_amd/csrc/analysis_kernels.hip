@@ -48,8 +48,10 @@ __global__ void k_pack(const float* __restrict__ s, int n, float2* __restrict__ 
 }
 
 // FFT of every row (one block per row), unnormalised; INV uses the conjugate
-// twiddles w_k = exp(+2 pi i k / n).  Bit-reversed load into LDS, then the radix-2
-// decimation-in-time stages in pairs: a thread takes four points, applies the
+// twiddles w_k = exp(+2 pi i k / n), both from the table of k_twiddles (the
+// values sincospif gives, computed once per handle instead of once per row).
+// Bit-reversed load into LDS, then the radix-2 decimation-in-time stages in
+// pairs: a thread takes four points, applies the
 // butterflies of two consecutive stages in registers and writes them back, so a
 // pair costs one LDS round trip and one barrier (an odd last stage runs alone).
 // The butterflies and twiddles are those of the plain radix-2 form, in the same
@@ -62,17 +64,26 @@ __device__ __forceinline__ void butterfly(float2& u, float2& v, float2 w) {
   u = make_float2(a.x + t.x, a.y + t.y);
   v = make_float2(a.x - t.x, a.y - t.y);
 }
+// Forward twiddles w_k = exp(-2 pi i k / n), k < n / 2 (computed once per handle).
+__global__ void k_twiddles(float2* __restrict__ tw, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n / 2) return;
+  float sn, cs;
+  sincospif(2.f * (float)k / (float)n, &sn, &cs);
+  tw[k] = make_float2(cs, -sn);
+}
+
 template <bool INV>
-__global__ void __launch_bounds__(256) k_fft_rows(float2* __restrict__ data, int n, int logn) {
+__global__ void __launch_bounds__(256) k_fft_rows(float2* __restrict__ data, const float2* __restrict__ twg, int n,
+                                                  int logn) {
   extern __shared__ float2 sm[];
   float2* buf = sm;
   float2* tw = sm + n + (n >> 5);
   float2* row = data + (size_t)blockIdx.x * n;
   for (int i = threadIdx.x; i < n; i += 256) buf[lds_pad(__brev((unsigned)i) >> (32 - logn))] = row[i];
   for (int k = threadIdx.x; k < n / 2; k += 256) {
-    float sn, cs;
-    sincospif(2.f * (float)k / (float)n, &sn, &cs);
-    tw[k] = make_float2(cs, INV ? sn : -sn);
+    const float2 w = twg[k];
+    tw[k] = INV ? make_float2(w.x, -w.y) : w;
   }
   __syncthreads();
   int lh = 0;
@@ -356,14 +367,19 @@ hipError_t launch_pack(const float* s, int n, float2* za, float2* zb, float2* zc
   return hipGetLastError();
 }
 
-hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, hipStream_t st) {
+hipError_t launch_twiddles(float2* tw, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3((n / 2 + 255) / 256), dim3(256), 0, st, tw, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft2t(float2* in, float2* out, int n, int logn, bool inverse, const float2* tw, hipStream_t st) {
   const size_t lds = (size_t)(n + (n >> 5) + n / 2) * sizeof(float2);
   const dim3 tg((n + 31) / 32, (n + 31) / 32), tb(32, 8);
-  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, in, n, logn);
-  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, in, n, logn);
+  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, in, tw, n, logn);
+  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, in, tw, n, logn);
   hipLaunchKernelGGL(k_transpose, tg, tb, 0, st, in, out, n);
-  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, out, n, logn);
-  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, out, n, logn);
+  if (inverse) hipLaunchKernelGGL(k_fft_rows<true>, dim3(n), dim3(256), lds, st, out, tw, n, logn);
+  else hipLaunchKernelGGL(k_fft_rows<false>, dim3(n), dim3(256), lds, st, out, tw, n, logn);
   return hipGetLastError();
 }
 

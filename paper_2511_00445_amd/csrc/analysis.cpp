@@ -2,7 +2,9 @@
 // and the kernel sequences of the spectra, correlations, overlaps and defects.
 #include "tfan_analysis.h"
 
+#include <cstring>
 #include <string>
+#include <vector>
 
 #include "analysis_internal.h"
 
@@ -27,7 +29,7 @@ int shell_of(long long m2) {
 }
 
 struct Plan {
-  size_t z[3], scratch, w[2], pE, pS, partial, pcount, out, red, dpart, dout, tw, total;
+  size_t z[3], scratch, w[2], pE, pS, partial, pcount, out, red, dpart, res, tw, total;
 };
 
 Plan plan(int n, int ns) {
@@ -47,10 +49,10 @@ Plan plan(int n, int ns) {
   p.pS = take(r);
   p.partial = take((size_t)3 * n * ns * 8);
   p.pcount = take((size_t)n * ns * 4);
-  p.out = take((size_t)(4 * ns + 1) * 8);
+  p.out = take(6 * 8);  // overlaps
   p.red = take((size_t)tana::reduce_blocks(n) * 6 * 8 + 64);
   p.dpart = take((size_t)tana::reduce_blocks(n) * 2 * 8);
-  p.dout = take(2 * 8);
+  p.res = take((size_t)(8 * ns + 3) * 8);
   p.tw = take((size_t)(n / 2) * 8);
   p.total = o;
   return p;
@@ -64,8 +66,15 @@ struct tfan_analysis {
   char* base = nullptr;
   Plan p{};
   std::string err;
+  std::vector<double> host;  // staging of the result block
   template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
   const float2* twiddles() const { return at<float2>(p.tw); }
+  // Result block on the device: spectra E, S, W, count, L (4 ns + 1), then the
+  // correlations Cuu, Cww, CQQ, count (4 ns), then the defect counts (2), so that
+  // any call reads its results back in one copy.
+  size_t corr_at() const { return (size_t)4 * ns + 1; }
+  size_t def_at() const { return (size_t)8 * ns + 1; }
+  double* res(size_t at_) const { return at<double>(p.res) + at_; }
 };
 
 namespace {
@@ -103,49 +112,60 @@ int transforms(tfan_analysis* a, const float* s) {
   return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "transforms");
 }
 
-// Shell sums of the spectra and L from the transforms; results copied out
-// (stream-ordered, before any later kernel reuses the output buffer).
-int spectra_from_transforms(tfan_analysis* a, double* E, double* W, double* S, double* count, double* L) {
-  const int ns = a->ns;
-  double* out = a->at<double>(a->p.out);
-  hipError_t e = tana::launch_shells(a->at<float>(a->p.pE), a->at<float>(a->p.pS), nullptr, 1, a->n, ns, false,
+// Shell sums of the spectra and L from the transforms, into the result block.
+int spectra_enqueue(tfan_analysis* a) {
+  double* out = a->res(0);
+  hipError_t e = tana::launch_shells(a->at<float>(a->p.pE), a->at<float>(a->p.pS), nullptr, 1, a->n, a->ns, false,
                                      a->at<double>(a->p.partial), a->at<int>(a->p.pcount), out, a->stream);
-  if (e == hipSuccess) e = tana::launch_finish_spectra(out, a->n, ns, a->stream);
-  if (e != hipSuccess) return hip_fail(a, e, "spectra");
-  int rc;
-  if ((rc = copy_out(a, E, out, ns)) || (rc = copy_out(a, S, out + ns, ns)) || (rc = copy_out(a, W, out + 2 * ns, ns)) ||
-      (rc = copy_out(a, count, out + 3 * ns, ns)) || (rc = copy_out(a, L, out + 4 * ns, 1)))
-    return rc;
-  return TFAN_OK;
+  if (e == hipSuccess) e = tana::launch_finish_spectra(out, a->n, a->ns, a->stream);
+  return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "spectra");
 }
 
 // Inverse transforms of the (transposed) powers, which come out in natural
-// layout, and their shell means; results copied out.
-int correlations_from_transforms(tfan_analysis* a, double* Cuu, double* Cww, double* CQQ, double* count) {
+// layout, and their shell means, into the result block.
+int correlations_enqueue(tfan_analysis* a) {
   float2* c0 = a->at<float2>(a->p.z[2]);
   float2* c1 = a->at<float2>(a->p.scratch);
   hipError_t e = tana::launch_fft2t(a->at<float2>(a->p.w[0]), c0, a->n, a->logn, true, a->twiddles(), a->stream);
   if (e == hipSuccess) e = tana::launch_fft2t(a->at<float2>(a->p.w[1]), c1, a->n, a->logn, true, a->twiddles(), a->stream);
-  const int ns = a->ns;
-  double* out = a->at<double>(a->p.out);
   if (e == hipSuccess)
     e = tana::launch_shells(reinterpret_cast<const float*>(c0), reinterpret_cast<const float*>(c0) + 1,
-                            reinterpret_cast<const float*>(c1), 2, a->n, ns, true, a->at<double>(a->p.partial),
-                            a->at<int>(a->p.pcount), out, a->stream);
-  if (e != hipSuccess) return hip_fail(a, e, "correlations");
-  int rc;
-  if ((rc = copy_out(a, Cuu, out, ns)) || (rc = copy_out(a, Cww, out + ns, ns)) ||
-      (rc = copy_out(a, CQQ, out + 2 * ns, ns)) || (rc = copy_out(a, count, out + 3 * ns, ns)))
-    return rc;
-  return TFAN_OK;
+                            reinterpret_cast<const float*>(c1), 2, a->n, a->ns, true, a->at<double>(a->p.partial),
+                            a->at<int>(a->p.pcount), a->res(a->corr_at()), a->stream);
+  return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "correlations");
 }
 
-// Defect counts into the host pair (stream-ordered copy; the caller synchronises).
-int defects_enqueue(tfan_analysis* a, const float* s, double* host2) {
-  double* d = a->at<double>(a->p.dout);
-  hipError_t e = tana::launch_defects(s, a->n, a->at<double>(a->p.dpart), d, a->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(host2, d, 16, hipMemcpyDeviceToHost, a->stream);
+// Defect counts into the result block.
+int defects_enqueue(tfan_analysis* a, const float* s) {
+  hipError_t e = tana::launch_defects(s, a->n, a->at<double>(a->p.dpart), a->res(a->def_at()), a->stream);
   return e == hipSuccess ? TFAN_OK : hip_fail(a, e, "defects");
+}
+
+// One read-back of result-block entries [from, from + count), then synchronise.
+int fetch(tfan_analysis* a, size_t from, size_t count) {
+  hipError_t e = hipMemcpyAsync(a->host.data() + from, a->res(from), count * 8, hipMemcpyDeviceToHost, a->stream);
+  if (e != hipSuccess) return hip_fail(a, e, "read-back");
+  return finish(a);
+}
+void put(double* dst, const double* src, size_t count) {
+  if (dst) std::memcpy(dst, src, count * 8);
+}
+void put_spectra(const tfan_analysis* a, double* E, double* W, double* S, double* count, double* L) {
+  const double* h = a->host.data();
+  const size_t ns = (size_t)a->ns;
+  put(E, h, ns);
+  put(S, h + ns, ns);
+  put(W, h + 2 * ns, ns);
+  put(count, h + 3 * ns, ns);
+  put(L, h + 4 * ns, 1);
+}
+void put_correlations(const tfan_analysis* a, double* Cuu, double* Cww, double* CQQ, double* count) {
+  const double* h = a->host.data() + a->corr_at();
+  const size_t ns = (size_t)a->ns;
+  put(Cuu, h, ns);
+  put(Cww, h + ns, ns);
+  put(CQQ, h + 2 * ns, ns);
+  put(count, h + 3 * ns, ns);
 }
 
 }  // namespace
@@ -177,6 +197,7 @@ int tfan_analysis_create(int32_t n, void* ws, size_t bytes, void* stream, tfan_a
   a->stream = (hipStream_t)stream;
   a->base = (char*)ws;
   a->p = p;
+  a->host.assign((size_t)8 * ns + 3, 0.0);
   // the FFT twiddle table, enqueued on the handle's stream ahead of every later call
   hipError_t e = tana::launch_twiddles(a->at<float2>(p.tw), n, a->stream);
   if (e != hipSuccess) {
@@ -191,20 +212,21 @@ int tfan_analysis_spectra(tfan_analysis* a, const float* s, double* E, double* W
                           double* L) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
-  int rc = transforms(a, s);
-  if (rc) return rc;
-  rc = spectra_from_transforms(a, E, W, S, count, L);
-  return rc ? rc : finish(a);
+  int rc;
+  if ((rc = transforms(a, s)) || (rc = spectra_enqueue(a)) || (rc = fetch(a, 0, a->corr_at()))) return rc;
+  put_spectra(a, E, W, S, count, L);
+  return TFAN_OK;
 }
 
 int tfan_analysis_correlations(tfan_analysis* a, const float* s, double* Cuu, double* Cww, double* CQQ,
                                double* count) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
-  int rc = transforms(a, s);
-  if (rc) return rc;
-  rc = correlations_from_transforms(a, Cuu, Cww, CQQ, count);
-  return rc ? rc : finish(a);
+  int rc;
+  if ((rc = transforms(a, s)) || (rc = correlations_enqueue(a)) || (rc = fetch(a, a->corr_at(), (size_t)4 * a->ns)))
+    return rc;
+  put_correlations(a, Cuu, Cww, CQQ, count);
+  return TFAN_OK;
 }
 
 int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, double* out) {
@@ -220,12 +242,10 @@ int tfan_analysis_overlaps(tfan_analysis* a, const float* s0, const float* s1, d
 int tfan_analysis_defects(tfan_analysis* a, const float* s, int64_t* plus, int64_t* minus) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s || !plus || !minus) return fail(a, TFAN_EINVAL, "NULL argument");
-  double h[2] = {0, 0};
-  int rc = defects_enqueue(a, s, h);
-  if (rc) return rc;
-  if ((rc = finish(a))) return rc;
-  *plus = (int64_t)h[0];
-  *minus = (int64_t)h[1];
+  int rc;
+  if ((rc = defects_enqueue(a, s)) || (rc = fetch(a, a->def_at(), 2))) return rc;
+  *plus = (int64_t)a->host[a->def_at()];
+  *minus = (int64_t)a->host[a->def_at() + 1];
   return TFAN_OK;
 }
 
@@ -233,15 +253,14 @@ int tfan_analysis_all(tfan_analysis* a, const float* s, double* E, double* W, do
                       double* Cww, double* CQQ, double* count, int64_t* plus, int64_t* minus) {
   if (!a) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!s) return fail(a, TFAN_EINVAL, "state is NULL");
-  int rc = transforms(a, s);
-  if (rc) return rc;
-  if ((rc = spectra_from_transforms(a, E, W, S, count, L))) return rc;
-  if ((rc = correlations_from_transforms(a, Cuu, Cww, CQQ, nullptr))) return rc;
-  double h[2] = {0, 0};
-  if ((rc = defects_enqueue(a, s, h))) return rc;
-  if ((rc = finish(a))) return rc;
-  if (plus) *plus = (int64_t)h[0];
-  if (minus) *minus = (int64_t)h[1];
+  int rc;
+  if ((rc = transforms(a, s)) || (rc = spectra_enqueue(a)) || (rc = correlations_enqueue(a)) ||
+      (rc = defects_enqueue(a, s)) || (rc = fetch(a, 0, a->def_at() + 2)))
+    return rc;
+  put_spectra(a, E, W, S, count, L);
+  put_correlations(a, Cuu, Cww, CQQ, nullptr);
+  if (plus) *plus = (int64_t)a->host[a->def_at()];
+  if (minus) *minus = (int64_t)a->host[a->def_at() + 1];
   return TFAN_OK;
 }
 

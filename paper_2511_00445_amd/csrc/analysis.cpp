@@ -47,8 +47,9 @@ Plan plan(int n, int ns) {
   p.w[1] = take(c);
   p.pE = take(r);
   p.pS = take(r);
-  p.partial = take((size_t)3 * n * ns * 8);
-  p.pcount = take((size_t)n * ns * 4);
+  const size_t nb = (size_t)(n + 255) / 256;  // row blocks of the shell sums
+  p.partial = take(3 * nb * ns * 8);
+  p.pcount = take(nb * ns * 4);
   p.out = take(6 * 8);  // overlaps
   p.red = take((size_t)tana::reduce_blocks(n) * 6 * 8 + 64);
   p.dpart = take((size_t)tana::reduce_blocks(n) * 2 * 8);

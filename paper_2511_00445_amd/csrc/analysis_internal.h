@@ -21,7 +21,7 @@ hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, in
                         float2* w0, float2* w1, hipStream_t st);
 // Shell sums of up to three inputs (element e at in_c[stride * e]) into out[4][ns]
 // (three sums and the counts); mean: divide by the value at the origin and by the
-// count (correlation maps).  partial: 3 ns n doubles, pcount: ns n ints.
+// count (correlation maps).  partial: 3 ns nb doubles, pcount: ns nb ints, nb = ceil(n / 256) row blocks.
 hipError_t launch_shells(const float* in0, const float* in1, const float* in2, int stride, int n, int ns, bool mean,
                          double* partial, int* pcount, double* out, hipStream_t st);
 // W = k^2 E into out[2 ns ..) and L into out[4 ns].

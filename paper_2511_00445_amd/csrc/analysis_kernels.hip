@@ -167,14 +167,16 @@ __device__ __forceinline__ int isqrt_floor(int v) {
 // Shell sums, one thread per (shell s, row j): the sites of row j in shell s are
 // those with (s - 1/2)^2 <= fx^2 + fy^2 < (s + 1/2)^2, i.e. fx^2 in
 // [s^2 - s + 1 - fy^2, s^2 + s - fy^2] (s = 0: fx = fy = 0), an interval of |fx|
-// taken at +fx and -fx.  Each thread sums its sites in a fixed order and writes
-// partial[c][s][j] (three inputs, element e at in_c[stride * e]) and the count.
-__global__ void k_shell_part(const float* __restrict__ in0, const float* __restrict__ in1,
-                             const float* __restrict__ in2, int stride, int n, int ns,
-                             double* __restrict__ partial, int* __restrict__ pcount) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
-  if (j >= n) return;
-  const int fy = freq(j, n), f2 = fy * fy, half = n / 2;
+// taken at +fx and -fx.  Each thread sums its sites in a fixed order; the block's
+// 256 rows are then added by a fixed tree, and the block writes
+// partial[c][s][b] (three inputs, element e at in_c[stride * e]) and the count
+// (b = row block; n / 256 partials per shell instead of n).
+__global__ void __launch_bounds__(256) k_shell_part(const float* __restrict__ in0, const float* __restrict__ in1,
+                                                   const float* __restrict__ in2, int stride, int n, int ns,
+                                                   double* __restrict__ partial, int* __restrict__ pcount) {
+  __shared__ double red[4][256];
+  const int t = threadIdx.x, j = blockIdx.x * 256 + t, s = blockIdx.y;
+  const int fy = freq(j < n ? j : 0, n), f2 = j < n ? fy * fy : 0x7fffffff, half = n / 2;
   const int lo = s == 0 ? 0 : s * s - s + 1, hi = s == 0 ? 0 : s * s + s;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int c = 0;
@@ -196,25 +198,38 @@ __global__ void k_shell_part(const float* __restrict__ in0, const float* __restr
       }
     }
   }
-  const size_t plane = (size_t)ns * n, o = (size_t)s * n + j;
-  partial[o] = a0;
-  partial[plane + o] = a1;
-  partial[2 * plane + o] = a2;
-  pcount[o] = c;
+  red[0][t] = a0;
+  red[1][t] = a1;
+  red[2][t] = a2;
+  red[3][t] = (double)c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + w];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const int nb = gridDim.x;
+    const size_t plane = (size_t)ns * nb, o = (size_t)s * nb + blockIdx.x;
+    partial[o] = red[0][0];
+    partial[plane + o] = red[1][0];
+    partial[2 * plane + o] = red[2][0];
+    pcount[o] = (int)red[3][0];
+  }
 }
 
-// Sum over rows of every shell (one block per shell, fixed strided assignment and
-// fixed tree); mean: divide by the value at the origin of the input and by the
-// count (correlation maps).
+// Sum over the row blocks of every shell (one block per shell, fixed strided
+// assignment and fixed tree); mean: divide by the value at the origin of the
+// input and by the count (correlation maps).
 __global__ void __launch_bounds__(256) k_shell_sum(const double* __restrict__ partial, const int* __restrict__ pcount,
-                                                   int n, int ns, const float* __restrict__ in0,
+                                                   int nb, int ns, const float* __restrict__ in0,
                                                    const float* __restrict__ in1, const float* __restrict__ in2,
                                                    int mean, double* __restrict__ out) {
   __shared__ double red[4][256];
   const int s = blockIdx.x, t = threadIdx.x;
-  const size_t plane = (size_t)ns * n, base = (size_t)s * n;
+  const size_t plane = (size_t)ns * nb, base = (size_t)s * nb;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, c = 0.0;
-  for (int j = t; j < n; j += 256) {
+  for (int j = t; j < nb; j += 256) {
     a0 += partial[base + j];
     a1 += partial[plane + base + j];
     a2 += partial[2 * plane + base + j];
@@ -394,11 +409,13 @@ hipError_t launch_power(const float2* za, const float2* zb, const float2* zc, in
 
 hipError_t launch_shells(const float* in0, const float* in1, const float* in2, int stride, int n, int ns, bool mean,
                          double* partial, int* pcount, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_shell_part, dim3((n + 255) / 256, ns), dim3(256), 0, st, in0, in1, in2, stride, n, ns, partial,
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_shell_part, dim3(nb, ns), dim3(256), 0, st, in0, in1, in2, stride, n, ns, partial,
                      pcount);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_shell_sum, dim3(ns), dim3(256), 0, st, partial, pcount, n, ns, in0, in1, in2, mean ? 1 : 0, out);
+  hipLaunchKernelGGL(k_shell_sum, dim3(ns), dim3(256), 0, st, partial, pcount, nb, ns, in0, in1, in2, mean ? 1 : 0,
+                     out);
   return hipGetLastError();
 }
 

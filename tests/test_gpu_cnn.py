@@ -69,6 +69,32 @@ def test_forward_matches_oracle(gpu):
     assert rel(got - X, ref - X) <= 2e-3
 
 
+def test_forward_matches_oracle_when_blocks_walk_several_tiles(gpu):
+    """Three 256 x 256 samples: 768 tiles of 16 x 16 sites, more than the
+    persistent grid's 512 blocks, so blocks walk two tiles and take the path that
+    loads the next tile while the matrix cores work on the current one; tiles of
+    different samples share blocks."""
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn forward B=3 256x256 (blocks walk several tiles)")
+    layers, theta, scales, X, _ = setup(3, 3, 256, 256)
+    net = Cnn(3, 256, 256)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    x = torch.from_numpy(X).cuda()
+    out = torch.empty_like(x)
+    net.forward(x, out)
+    net.sync()
+    got = out.cpu().numpy().astype(np.float64)
+    so = scales[1].astype(np.float64)[None, :, None, None]
+    y_ref, _ = C.forward(layers, X.astype(np.float64) * inv(scales[0]))
+    e = rel((got - X) / so, y_ref)
+    say(f"forward 3 x 256^2: relative L2 of the network output {e:.2e}")
+    assert e <= 2e-3
+    for b in range(3):  # each sample on its own, so that no sample is mixed up with another
+        assert rel((got[b] - X[b]) / so[0], y_ref[b]) <= 2e-3, b
+
+
 def test_gradients_match_oracle(gpu):
     import torch
     from paper_2511_00445_amd import Cnn

@@ -117,6 +117,31 @@ def test_gradients_match_oracle(gpu):
         assert ew <= 5e-3 and eb <= 5e-3, (li, ew, eb)
 
 
+def test_gradients_match_oracle_when_blocks_walk_several_tiles(gpu):
+    """Three 256 x 256 samples (768 tiles): the convolutions' persistent blocks
+    (512) and the weight-gradient blocks (256) each walk several tiles, and the
+    block partials of every layer's weight gradient are reduced over 256 blocks."""
+    import torch
+    from paper_2511_00445_amd import Cnn
+    say("case: cnn gradients B=3 256x256 (blocks walk several tiles)")
+    layers, theta, scales, X, T = setup(4, 3, 256, 256)
+    net = Cnn(3, 256, 256, train=True)
+    net.set_params(theta)
+    net.set_scales(*scales)
+    idx = [1, 2, 0]
+    loss, g = net.gradients(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), idx)
+    xn = X[idx].astype(np.float64) * inv(scales[0])
+    tn = (T[idx].astype(np.float32) - X[idx].astype(np.float32)).astype(np.float64) * inv(scales[1])
+    lref, gref = C.loss_and_grads(layers, xn, tn)
+    say(f"loss gpu {loss:.8e} oracle {lref:.8e}")
+    assert abs(loss - lref) <= 1e-4 * lref
+    gg = C.unflatten(g.astype(np.float64))
+    for li in range(C.LAYERS):
+        ew, eb = rel(gg[li][0], gref[li][0]), rel(gg[li][1], gref[li][1])
+        say(f"layer {li + 1}: dW rel L2 {ew:.2e}, db rel L2 {eb:.2e}")
+        assert ew <= 5e-3 and eb <= 5e-3, (li, ew, eb)
+
+
 def test_adam_step_closed_form(gpu):
     """First Adam step: bias-corrected moments are g and g^2, so each parameter
     moves by lr g / (|g| + eps) with g the batch gradient."""

@@ -72,7 +72,11 @@ typedef struct tfan_params {
   double gamma;        /* inter-fluid drag coefficient                           */
   double A_ch, kappa;  /* mu = A_ch (phi^3 - phi) - kappa lap(phi)               */
   double M;            /* Cahn-Hilliard mobility                                 */
-  double A_ldg, C_ldg; /* Landau-de Gennes (A/2) TrQ^2 + (C/4) TrQ^4 (Model Eq. 8) */
+  double A0, gamma_ldg; /* Landau-de Gennes bulk energy (Model Eq. 8) in the (A0,
+                        * gamma) form (A0/2)(1 - gamma/3) TrQ^2 - (A0 gamma/3) TrQ^3
+                        * + (A0 gamma/4)(TrQ^2)^2; the library uses A = A0 (1 - gamma/3)
+                        * and C = 2 A0 gamma of (A/2) TrQ^2 + (C/4) TrQ^4.  gamma = 3 is
+                        * the two-dimensional isotropic-nematic point (A = 0).          */
   double K;            /* Frank elastic constant                                 */
   double lam;          /* tumbling parameter lambda                              */
   double Gamma;        /* rotational diffusion constant                          */
@@ -96,7 +100,7 @@ typedef struct tfan_diag {
   double enstrophy_a;  /* sum omega_a^2, omega = d_x u_y - d_y u_x                */
   double enstrophy_c;  /* sum omega_c^2                                          */
   double elastic;      /* sum (K/2) |grad Q|^2, |grad Q|^2 = sum_kij (d_k Q_ij)^2 */
-  double s_sum;        /* sum S, S = sqrt(Qxx^2 + Qxy^2)                          */
+  double s_mean;       /* mean of S over sites, S = sqrt(Qxx^2 + Qxy^2) (Q = 2S(pp - I/2)) */
   double umax;         /* max over sites of max(|u_a|, |u_p|)                    */
 } tfan_diag;
 

@@ -18,7 +18,7 @@
 
 typedef struct {
   int nx, ny, n_sub;
-  double rho0, tau_a, tau_p, gamma, A_ch, kappa, M, A_ldg, C_ldg, K, lam, Gamma, zeta;
+  double rho0, tau_a, tau_p, gamma, A_ch, kappa, M, A0, gamma_ldg, K, lam, Gamma, zeta;
 } oc_params;
 
 typedef struct {
@@ -70,9 +70,15 @@ static double ddy(const double* g, int x, int y, int nx, int ny) {
   return 0.5 * (g[md(y + 1, ny) * nx + x] - g[md(y - 1, ny) * nx + x]);
 }
 
-/* molecular field H = -dF/dQ + (I/2) Tr(dF/dQ), F = (A/2)TrQ^2 + (C/4)TrQ^4 + (K/2)|grad Q|^2 */
+/* molecular field H = -dF/dQ + (I/2) Tr(dF/dQ), F = (A/2)TrQ^2 + (C/4)TrQ^4 + (K/2)|grad Q|^2
+ * (Model, Eqs. 7-8).  A and C come from the (A0, gamma) form of the Landau-de Gennes
+ * energy, (A0/2)(1 - gamma/3) TrQ^2 - (A0 gamma/3) TrQ^3 + (A0 gamma/4)(TrQ^2)^2:
+ * A = A0 (1 - gamma/3) and, as TrQ^4 = (TrQ^2)^2 / 2 for a 2x2 traceless Q,
+ * C = 2 A0 gamma.  The cubic term only adds a multiple of I to dF/dQ, which the
+ * traceless part removes, so it is left out. */
 static void molecular(const oc_sim* s, const double* qxx, const double* qxy, int x, int y, double* h) {
   const int nx = s->p.nx, ny = s->p.ny, i = y * nx + x;
+  const double A = s->p.A0 * (1.0 - s->p.gamma_ldg / 3.0), C = 2.0 * s->p.A0 * s->p.gamma_ldg;
   double q[4], q2[4], q3[4], lq[4], dF[4];
   qtensor(s, qxx, qxy, i, q);
   mat_mul(q, q, q2);
@@ -81,7 +87,7 @@ static void molecular(const oc_sim* s, const double* qxx, const double* qxy, int
   lq[1] = lap(qxy, x, y, nx, ny);
   lq[2] = lq[1];
   lq[3] = -lq[0];
-  for (int k = 0; k < 4; ++k) dF[k] = s->p.A_ldg * q[k] + s->p.C_ldg * q3[k] - s->p.K * lq[k];
+  for (int k = 0; k < 4; ++k) dF[k] = A * q[k] + C * q3[k] - s->p.K * lq[k];
   const double tr = dF[0] + dF[3];
   for (int k = 0; k < 4; ++k) h[k] = -dF[k];
   h[0] += 0.5 * tr;

@@ -14,7 +14,7 @@ _lib = None
 class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("n_sub", ctypes.c_int)] + [
         (k, ctypes.c_double) for k in ("rho0", "tau_a", "tau_p", "gamma", "A_ch", "kappa", "M",
-                                       "A_ldg", "C_ldg", "K", "lam", "Gamma", "zeta")]
+                                       "A0", "gamma_ldg", "K", "lam", "Gamma", "zeta")]
 
 
 def _load():

@@ -50,7 +50,7 @@ WI = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=np.float64)
 CS2 = 1.0 / 3.0  # lattice sound speed squared
 
 PARAM_KEYS = ("nx", "ny", "rho0", "tau_a", "tau_p", "gamma", "A_ch", "kappa", "M",
-              "A_ldg", "C_ldg", "K", "lam", "Gamma", "zeta", "n_sub")
+              "A0", "gamma_ldg", "K", "lam", "Gamma", "zeta", "n_sub")
 
 
 # ----------------------------------------------------------------------------
@@ -131,6 +131,15 @@ def capillary_force(phi, mu):
 # Landau-de Gennes / Beris-Edwards pieces (Model, Eqs. 7, 8, 11, 12 and the
 # elastic stress display)
 # ----------------------------------------------------------------------------
+def landau_coefficients(A0, gamma_ldg):
+    """Bulk coefficients (A, B, C) of (A/2)TrQ^2 + (B/3)TrQ^3 + (C/4)TrQ^4 (Model, Eq. 8)
+    for the workloads' (A0, gamma) parameters.  Reading: the (A0, gamma) form of the
+    Landau-de Gennes energy, (A0/2)(1 - gamma/3) TrQ^2 - (A0 gamma/3) TrQ^3
+    + (A0 gamma/4)(TrQ^2)^2, written in the paper's form; for a symmetric traceless
+    2x2 Q, TrQ^4 = (TrQ^2)^2 / 2, so the quartic coefficient is C = 2 A0 gamma."""
+    return A0 * (1.0 - gamma_ldg / 3.0), -A0 * gamma_ldg, 2.0 * A0 * gamma_ldg
+
+
 def free_energy_derivative(Q, A, B, C, K):
     """dF/dQ of F = (A/2)TrQ^2 + (B/3)TrQ^3 + (C/4)TrQ^4 + (K/2)|grad Q|^2 (Model, Eq. 8)."""
     Q2 = mm(Q, Q)
@@ -183,7 +192,8 @@ def corotation(W, Q, lam):
 
 def be_rhs(Q, ua, W, p):
     """Full-tensor right-hand side of d_t Q = -u_a.grad Q + S(W, Q) + Gamma H (Model, Eq. 11)."""
-    H = molecular_field(Q, p["A_ldg"], p["C_ldg"], p["K"])
+    A, B, C = landau_coefficients(p["A0"], p["gamma_ldg"])
+    H = molecular_field(Q, A, C, p["K"], B=B)
     adv = -(ua[0] * d_x(Q) + ua[1] * d_y(Q))
     return adv + corotation(W, Q, p["lam"]) + p["Gamma"] * H
 
@@ -292,7 +302,8 @@ class Oracle:
         c2 = 0.5 * (1.0 - phi)
         mu = chemical_potential(phi, p["A_ch"], p["kappa"])
         Q = q_tensor(self.qxx, self.qxy)
-        H = molecular_field(Q, p["A_ldg"], p["C_ldg"], p["K"])
+        A, B, C = landau_coefficients(p["A0"], p["gamma_ldg"])
+        H = molecular_field(Q, A, C, p["K"], B=B)
         sigma = elastic_stress(Q, H, p["lam"], p["K"]) + active_stress(Q, c1, p["zeta"])
         F_el_act = divergence(sigma)
         F_ch = capillary_force(phi, mu)
@@ -339,54 +350,84 @@ class Oracle:
                     u_a=mac["u_a"], u_p=mac["u_p"], rho_a=mac["rho_a"], rho_p=mac["rho_p"])
 
     def diagnostics(self) -> dict:
-        """FP64 sums of the observables (Results: u_c, omega_c, Delta, energies, rms values)."""
+        """FP64 sums of the Results-section observables over all sites (site_observables),
+        plus the count of non-finite state values."""
         p = self.p
         mac = self.macroscopic()
-        ua, up, uc = mac["u_a"], mac["u_p"], mac["u_c"]
-        w_a = d_x(ua[1]) - d_y(ua[0])
-        w_c = d_x(uc[1]) - d_y(uc[0])
-        Q = mac["Q"]
-        dQ = np.array([d_x(Q), d_y(Q)])
-        grad_q_sq = (dQ ** 2).sum(axis=(0, 1, 2))
-        ua2 = ua[0] ** 2 + ua[1] ** 2
-        up2 = up[0] ** 2 + up[1] ** 2
-        uc2 = uc[0] ** 2 + uc[1] ** 2
+        obs = site_observables(self.phi, self.qxx, self.qxy, mac["rho_a"], mac["rho_p"],
+                               mac["u_a"], mac["u_p"], p["K"])
         fields = [self.phi, self.qxx, self.qxy, self.f_a, self.f_p]
         nonfinite = int(sum(np.count_nonzero(~np.isfinite(a)) for a in fields))
-        return dict(
-            step=self.step_count,
-            phi_sum=float(self.phi.sum()),
-            phi_sq_sum=float((self.phi ** 2).sum()),
-            mass_a=float(mac["rho_a"].sum()),
-            mass_p=float(mac["rho_p"].sum()),
-            ke_a=float(0.5 * (mac["rho_a"] * ua2).sum()),
-            ke_p=float(0.5 * (mac["rho_p"] * up2).sum()),
-            ke_c=float(0.5 * uc2.sum()),
-            ua_sq=float(ua2.sum()),
-            uc_sq=float(uc2.sum()),
-            enstrophy_a=float((w_a ** 2).sum()),
-            enstrophy_c=float((w_c ** 2).sum()),
-            elastic=float(0.5 * p["K"] * grad_q_sq.sum()),
-            s_sum=float(np.sqrt(self.qxx ** 2 + self.qxy ** 2).sum()),
-            umax=float(np.sqrt(np.maximum(ua2, up2)).max()),
-            nonfinite=nonfinite,
-        )
+        out = dict(step=self.step_count, nonfinite=nonfinite)
+        for k in ("phi_sum", "phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p", "ke_c", "ua_sq", "uc_sq",
+                  "enstrophy_a", "enstrophy_c", "elastic"):
+            out[k] = float(obs[k].sum())
+        out["s_mean"] = float(obs["S"].mean())
+        out["umax"] = float(obs["speed"].max())
+        return out
 
     def free_energy(self) -> float:
         """Total free energy plus kinetic energy of both fluids (used by the passive
-        energy-decay check): bulk CH + gradient CH + LdG bulk + Frank + kinetic."""
+        energy-decay check): sum over sites of free_energy_density."""
         p = self.p
         mac = self.macroscopic()
-        phi = self.phi
-        e_ch = 0.25 * p["A_ch"] * (phi ** 2 - 1.0) ** 2 + 0.5 * p["kappa"] * (d_x(phi) ** 2 + d_y(phi) ** 2)
-        Q = mac["Q"]
-        trq2 = ddot(Q, Q)
-        trq4 = np.einsum("ii...->...", mm(mm(Q, Q), mm(Q, Q)))
-        dQ = np.array([d_x(Q), d_y(Q)])
-        e_q = 0.5 * p["A_ldg"] * trq2 + 0.25 * p["C_ldg"] * trq4 + 0.5 * p["K"] * (dQ ** 2).sum(axis=(0, 1, 2))
-        ua, up = mac["u_a"], mac["u_p"]
-        e_k = 0.5 * mac["rho_a"] * (ua ** 2).sum(0) + 0.5 * mac["rho_p"] * (up ** 2).sum(0)
-        return float((e_ch + e_q + e_k).sum())
+        return float(free_energy_density(self.phi, mac["Q"], mac["rho_a"], mac["rho_p"],
+                                         mac["u_a"], mac["u_p"], p).sum())
+
+
+# ----------------------------------------------------------------------------
+# Observables (Results section): per-site densities whose sums are the
+# diagnostics, and the free-energy functional of the Model section
+# ----------------------------------------------------------------------------
+def vorticity(u):
+    """omega = d_x u_y - d_y u_x (central differences)."""
+    return d_x(u[1]) - d_y(u[0])
+
+
+def kinetic_density(rho, u):
+    """(1/2) rho |u|^2."""
+    return 0.5 * rho * (u[0] ** 2 + u[1] ** 2)
+
+
+def frank_density(Q, K):
+    """(K/2) |grad Q|^2 with |grad Q|^2 = sum over k, i, j of (d_k Q_ij)^2: all four
+    entries of the full tensor, so each independent component counts twice."""
+    dQ = np.array([d_x(Q), d_y(Q)])
+    return 0.5 * K * (dQ ** 2).sum(axis=(0, 1, 2))
+
+
+def scalar_order(qxx, qxy):
+    """S with Q = 2 S (pp - I/2): the eigenvalues of Q are +-S."""
+    return np.sqrt(qxx ** 2 + qxy ** 2)
+
+
+def site_observables(phi, qxx, qxy, rho_a, rho_p, ua, up, K):
+    """Per-site densities of the diagnostic sums: phi, phi^2 (composition and its
+    variance Delta), both densities, kinetic energies (1/2) rho_s |u_s|^2 of each
+    fluid and (1/2)|u_c|^2 of the mixture velocity u_c = c1 u_a + c2 u_p, |u_a|^2,
+    |u_c|^2, enstrophy densities omega_a^2 and omega_c^2, the Frank elastic energy
+    density, the scalar order S and the larger of the two speeds."""
+    c1 = 0.5 * (1.0 + phi)
+    uc = c1 * ua + (1.0 - c1) * up
+    return dict(phi_sum=phi, phi_sq_sum=phi ** 2, mass_a=rho_a, mass_p=rho_p,
+                ke_a=kinetic_density(rho_a, ua), ke_p=kinetic_density(rho_p, up),
+                ke_c=kinetic_density(1.0, uc),
+                ua_sq=ua[0] ** 2 + ua[1] ** 2, uc_sq=uc[0] ** 2 + uc[1] ** 2,
+                enstrophy_a=vorticity(ua) ** 2, enstrophy_c=vorticity(uc) ** 2,
+                elastic=frank_density(q_tensor(qxx, qxy), K), S=scalar_order(qxx, qxy),
+                speed=np.sqrt(np.maximum(ua[0] ** 2 + ua[1] ** 2, up[0] ** 2 + up[1] ** 2)))
+
+
+def free_energy_density(phi, Q, rho_a, rho_p, ua, up, p):
+    """Bulk and gradient Cahn-Hilliard energy (A_ch/4)(phi^2 - 1)^2 + (kappa/2)|grad phi|^2,
+    Landau-de Gennes bulk (A/2)TrQ^2 + (B/3)TrQ^3 + (C/4)TrQ^4 (Model, Eq. 8), Frank
+    energy (K/2)|grad Q|^2 and the kinetic energy of both fluids."""
+    e_ch = 0.25 * p["A_ch"] * (phi ** 2 - 1.0) ** 2 + 0.5 * p["kappa"] * (d_x(phi) ** 2 + d_y(phi) ** 2)
+    A, B, C = landau_coefficients(p["A0"], p["gamma_ldg"])
+    Q2 = mm(Q, Q)
+    tr = lambda T: T[0, 0] + T[1, 1]
+    e_q = 0.5 * A * tr(Q2) + B / 3.0 * tr(mm(Q2, Q)) + 0.25 * C * tr(mm(Q2, Q2)) + frank_density(Q, p["K"])
+    return e_ch + e_q + kinetic_density(rho_a, ua) + kinetic_density(rho_p, up)
 
 
 # ----------------------------------------------------------------------------

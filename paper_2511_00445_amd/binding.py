@@ -23,8 +23,8 @@ class tfan_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("n_sub", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("rho0", ctypes.c_double), ("tau_a", ctypes.c_double),
                 ("tau_p", ctypes.c_double), ("gamma", ctypes.c_double), ("A_ch", ctypes.c_double),
-                ("kappa", ctypes.c_double), ("M", ctypes.c_double), ("A_ldg", ctypes.c_double),
-                ("C_ldg", ctypes.c_double), ("K", ctypes.c_double), ("lam", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("M", ctypes.c_double), ("A0", ctypes.c_double),
+                ("gamma_ldg", ctypes.c_double), ("K", ctypes.c_double), ("lam", ctypes.c_double),
                 ("Gamma", ctypes.c_double), ("zeta", ctypes.c_double)]
 
 
@@ -32,7 +32,7 @@ class tfan_diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64)] + [
         (k, ctypes.c_double) for k in ("phi_sum", "phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p",
                                        "ke_c", "ua_sq", "uc_sq", "enstrophy_a", "enstrophy_c",
-                                       "elastic", "s_sum", "umax")]
+                                       "elastic", "s_mean", "umax")]
 
 
 class TfanError(RuntimeError):

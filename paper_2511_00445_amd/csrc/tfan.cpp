@@ -65,7 +65,7 @@ std::string check(const tfan_params* p) {
   if (p->n_sub < 1 || p->n_sub > 8) return "n_sub must be in [1, 8]";
   if (p->storage != TFAN_STORAGE_F32 && p->storage != TFAN_STORAGE_F16) return "unsupported storage format";
   const double r[] = {p->rho0, p->tau_a, p->tau_p, p->gamma, p->A_ch, p->kappa, p->M,
-                      p->A_ldg, p->C_ldg, p->K, p->lam, p->Gamma, p->zeta};
+                      p->A0, p->gamma_ldg, p->K, p->lam, p->Gamma, p->zeta};
   for (double v : r)
     if (!std::isfinite(v)) return "parameters must be finite";
   if (!(p->rho0 > 0)) return "rho0 must be positive";
@@ -99,6 +99,9 @@ Layout layout(const tfan_params* p) {
   return L;
 }
 
+double ldg_A(const tfan_params* p) { return p->A0 * (1.0 - p->gamma_ldg / 3.0); }
+double ldg_C(const tfan_params* p) { return 2.0 * p->A0 * p->gamma_ldg; }
+
 DevParams dev_params(const tfan_params* p) {
   DevParams d{};
   d.nx = p->nx;
@@ -114,8 +117,14 @@ DevParams dev_params(const tfan_params* p) {
   d.A_ch = (float)p->A_ch;
   d.kappa = (float)p->kappa;
   d.M = (float)p->M;
-  d.A_ldg = (float)p->A_ldg;
-  d.halfC = (float)(0.5 * p->C_ldg);
+  // Landau-de Gennes bulk energy in the (A0, gamma) form,
+  // (A0/2)(1 - gamma/3) TrQ^2 - (A0 gamma/3) TrQ^3 + (A0 gamma/4)(TrQ^2)^2, written in the
+  // Model section's form (A/2)TrQ^2 + (B/3)TrQ^3 + (C/4)TrQ^4 (Eq. 8): A = A0 (1 - gamma/3),
+  // and C = 2 A0 gamma since TrQ^4 = (TrQ^2)^2 / 2 for a 2x2 traceless Q.  The cubic term
+  // adds only a multiple of I to dF/dQ and drops out of the traceless molecular field.
+  const double A_ldg = ldg_A(p), C_ldg = ldg_C(p);
+  d.A_ldg = (float)A_ldg;
+  d.halfC = (float)(0.5 * C_ldg);
   d.K = (float)p->K;
   d.lam = (float)p->lam;
   d.Gamma = (float)p->Gamma;
@@ -380,7 +389,7 @@ int tfan_diagnostics(tfan_sim* s, tfan_diag* out) {
   out->enstrophy_a = r[tfan::D_ENS_A];
   out->enstrophy_c = r[tfan::D_ENS_C];
   out->elastic = r[tfan::D_ELASTIC];
-  out->s_sum = r[tfan::D_S];
+  out->s_mean = r[tfan::D_S] / (double)s->dp.n;
   out->umax = r[tfan::D_UMAX];
   if (out->nonfinite > 0) return fail(s, TFAN_ENONFINITE, "state holds non-finite values");
   if (out->umax > 0.3) return fail(s, TFAN_EUNSTABLE, "max |u| exceeds 0.3");

@@ -14,7 +14,8 @@ Parameter names (shared by the C header, the binding and the oracle):
   tau_a, tau_p    BGK relaxation times of the active / passive fluid (viscosity (tau-1/2)/3)
   gamma           inter-fluid drag coefficient of F_drag
   A_ch, kappa, M  Cahn-Hilliard: mu = A_ch (phi^3 - phi) - kappa lap(phi), mobility M
-  A_ldg, C_ldg    Landau-de Gennes bulk coefficients A and C of (A/2)TrQ^2 + (C/4)TrQ^4
+  A0, gamma_ldg   Landau-de Gennes bulk energy in the (A0, gamma) form (gamma = 3: the
+                  two-dimensional isotropic-nematic point)
   K               Frank elastic constant
   lam             tumbling (flow-alignment) parameter lambda
   Gamma           rotational diffusion constant of the Beris-Edwards equation
@@ -26,29 +27,14 @@ from __future__ import annotations
 import numpy as np
 
 PARAM_NAMES = ("nx", "ny", "rho0", "tau_a", "tau_p", "gamma", "A_ch", "kappa", "M",
-               "A_ldg", "C_ldg", "K", "lam", "Gamma", "zeta", "n_sub")
-
-
-def ldg_from_a0_gamma(A0: float, gamma_ldg: float) -> tuple[float, float]:
-    """Landau-de Gennes coefficients (A, C) from the common (A0, gamma) form.
-
-    The (A0, gamma) form writes the bulk energy as
-    (A0/2)(1 - gamma/3) TrQ^2 - (A0 gamma/3) TrQ^3 + (A0 gamma/4)(TrQ^2)^2.
-    For a symmetric traceless Q, TrQ^4 = (TrQ^2)^2 / 2, so the quartic term equals
-    (C/4) TrQ^4 with C = 2 A0 gamma; the cubic term has no effect in two dimensions.
-    """
-    return A0 * (1.0 - gamma_ldg / 3.0), 2.0 * A0 * gamma_ldg
+               "A0", "gamma_ldg", "K", "lam", "Gamma", "zeta", "n_sub")
 
 
 def base_params(nx: int, ny: int, **over) -> dict:
     """The small-grid parameter set (64x64 case) with any field overridden."""
-    A_ldg, C_ldg = ldg_from_a0_gamma(0.1, 3.0)
     p = dict(nx=int(nx), ny=int(ny), rho0=1.0, tau_a=1.0, tau_p=1.0, gamma=0.01,
-             A_ch=0.04, kappa=0.04, M=0.1, A_ldg=A_ldg, C_ldg=C_ldg, K=0.04,
+             A_ch=0.04, kappa=0.04, M=0.1, A0=0.1, gamma_ldg=3.0, K=0.04,
              lam=0.7, Gamma=0.34, zeta=0.005, n_sub=5)
-    if "A0" in over or "gamma_ldg" in over:
-        A_ldg, C_ldg = ldg_from_a0_gamma(over.pop("A0", 0.1), over.pop("gamma_ldg", 3.0))
-        p["A_ldg"], p["C_ldg"] = A_ldg, C_ldg
     for k, v in over.items():
         if k not in p:
             raise KeyError(f"unknown parameter {k!r}")

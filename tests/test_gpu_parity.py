@@ -27,7 +27,11 @@ def say(msg):
 def rel_l2(g, o, floor=1e-8):
     """||g - o|| / ||o||, with ||o|| floored at floor * sqrt(size) so that fields
     that are zero up to rounding (the density deviations at rest) compare by an
-    absolute bound instead."""
+    absolute bound instead: below an RMS value of 1e-8 the bar TOL becomes an RMS
+    error of TOL * 1e-8 = 1e-12.  That is the float32 rounding of such a field:
+    rho - rho0 is a sum of nine stored deviations f_i - w_i rho0 of magnitude up to
+    ~1e-5 in these cases, each carrying a relative rounding of 2^-24 (6e-8), i.e.
+    ~6e-13 per term."""
     return float(np.linalg.norm(g - o) / max(np.linalg.norm(o), floor * np.sqrt(o.size)))
 
 
@@ -116,7 +120,7 @@ def test_diagnostics_match_oracle(gpu):
     d, od = sim.diagnostics(), o.diagnostics()
     assert d["status"] == 0 and d["step"] == od["step"] == 60 and d["nonfinite"] == 0
     for k in ("phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p", "ke_c", "ua_sq", "uc_sq",
-              "enstrophy_a", "enstrophy_c", "elastic", "s_sum", "umax"):
+              "enstrophy_a", "enstrophy_c", "elastic", "s_mean", "umax"):
         assert abs(d[k] - od[k]) <= 1e-4 * abs(od[k]) + 1e-12, (k, d[k], od[k])
     # phi mass: exact telescoping in the oracle; float32 drift measured and bounded
     assert abs(d["phi_sum"] - od["phi_sum"]) < 1e-4 * np.abs(ic["phi"]).sum()

@@ -15,6 +15,11 @@ def _P(Q):
     return Q + 0.5 * I2(Q.shape[2:])
 
 
+def _H(Q, p):
+    A, B, C = O.landau_coefficients(p["A0"], p["gamma_ldg"])
+    return O.molecular_field(Q, A, C, p["K"], B=B)
+
+
 def feq_quadratic(rho, u):                      # (c.u)^2 coefficient doubled
     cu = np.einsum("ia,a...->i...", O.CI.astype(float), u)
     uu = u[0] ** 2 + u[1] ** 2
@@ -90,7 +95,7 @@ MUTATIONS = [
      T.test_p11c_director_turns_with_shear_wave_vorticity, ()),
     ("BE: advection sign", "be_rhs",
      lambda Q, ua, W, p: ((ua[0] * O.d_x(Q) + ua[1] * O.d_y(Q)) + O.corotation(W, Q, p["lam"])
-                          + p["Gamma"] * O.molecular_field(Q, p["A_ldg"], p["C_ldg"], p["K"])),
+                          + p["Gamma"] * _H(Q, p)),
      T.test_p16_uniform_advection, ("qxx",)),
     ("drag with the wrong sign", "solve_velocities",
      lambda ra, ma, Ga, rp, mp, Gp, beta: O.solve_velocities(ra, ma, Ga, rp, mp, Gp, -beta),
@@ -104,6 +109,28 @@ MUTATIONS = [
     ("streaming against c_i", "stream",
      lambda fs: np.array([np.roll(fs[i], shift=(-O.CI[i, 1], -O.CI[i, 0]), axis=(0, 1)) for i in range(9)]),
      T.test_p19_acoustic_wave_direction_and_speed, ()),
+    # diagnostics and free energy (Results-section observables)
+    ("kinetic energy without 1/2", "kinetic_density", lambda rho, u: rho * (u[0] ** 2 + u[1] ** 2),
+     T.test_p20_diagnostics_shear_flows, ()),
+    ("Frank energy over the two stored components only", "frank_density",
+     lambda Q, K: 0.5 * K * sum(d(Q[0, c]) ** 2 for c in (0, 1) for d in (O.d_x, O.d_y)),
+     T.test_p20_diagnostics_frank_energy_and_order, ()),
+    ("vorticity with the wrong relative sign", "vorticity", lambda u: O.d_x(u[1]) + O.d_y(u[0]),
+     T.test_p20_diagnostics_cellular_flow_vorticity, ()),
+    ("mixture enstrophy from u_a", "site_observables",
+     lambda phi, qxx, qxy, ra, rp, ua, up, K: dict(
+         O.site_observables(phi, qxx, qxy, ra, rp, ua, up, K),
+         enstrophy_c=O.site_observables(phi, qxx, qxy, ra, rp, ua, ua, K)["enstrophy_c"]),
+     T.test_p20_diagnostics_shear_flows, ()),
+    ("mixture velocity with swapped fractions", "site_observables",
+     lambda phi, qxx, qxy, ra, rp, ua, up, K: O.site_observables(-phi, qxx, qxy, ra, rp, ua, up, K),
+     T.test_p20_diagnostics_cellular_flow_vorticity, ()),
+    ("scalar order without the square root", "scalar_order", lambda qxx, qxy: qxx ** 2 + qxy ** 2,
+     T.test_p20_diagnostics_frank_energy_and_order, ()),
+    ("LdG quartic coefficient A0 gamma", "landau_coefficients",
+     lambda A0, g: (A0 * (1 - g / 3), -A0 * g, A0 * g), T.test_p21_free_energy_uniform_nematic, (0.2, 5.0, 0.3)),
+    ("LdG quadratic coefficient without (1 - gamma/3)", "landau_coefficients",
+     lambda A0, g: (A0, -A0 * g, 2 * A0 * g), T.test_p21_free_energy_uniform_nematic, (0.1, 3.0, 0.1)),
 ]
 
 

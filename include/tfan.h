@@ -118,25 +118,42 @@ size_t tfan_workspace_bytes(const tfan_params* p);
 int tfan_create(const tfan_params* p, void* dev_workspace, size_t bytes,
                 void* hip_stream, tfan_sim** out);
 
-/* Set the state at step 0: phi, qxx, qxy [ny][nx]; u_a, u_p [2][ny][nx] or
- * NULL for zero.  Both population sets start at the D2Q9 equilibrium at
- * density rho0 and the given velocity.  Synchronises the stream. */
+/* Set the state at step 0 (Numerical Simulation: the initial composition,
+ * director field and fluid velocities): phi, qxx, qxy [ny][nx]; u_a, u_p
+ * [2][ny][nx] or NULL for zero.  Both population sets start at the D2Q9
+ * equilibrium f^eq(rho0, u) of the BGK collision.  Non-finite inputs:
+ * TFAN_EINVAL.  Synchronises the stream. */
 int tfan_init_fields(tfan_sim* s, const double* phi, const double* qxx,
                      const double* qxy, const double* u_a, const double* u_p);
 
 /* Enqueue n >= 0 coupled steps on the handle's stream; returns without
- * waiting. */
+ * waiting.  One step (Numerical Simulation) is: pull streaming of both D2Q9
+ * populations; moments; chemical potential mu (Model, Eq. 2 for the order
+ * parameter phi); molecular field H (Eq. 7 with the bulk energy of Eq. 8);
+ * elastic stress (Model, elastic stress display), active stress -zeta c1 Q and
+ * capillary force -phi grad(mu) (Eq. 10), their forces on each fluid; the
+ * half-force (Guo) velocities with the drag F_drag = gamma c1 c2 (u_p - u_a)
+ * solved implicitly per site; BGK collision with the Guo source for both
+ * fluids; then n_sub forward-Euler sub-steps of Eq. 1 (Cahn-Hilliard, advected
+ * by u_c) and Eqs. 11-12 (Beris-Edwards, advected and rotated by u_a) with the
+ * velocities frozen.  Gradients are second-order central differences and
+ * Laplacians 5-point stencils, all periodic.  n < 0: TFAN_EINVAL; a failed
+ * launch: TFAN_EHIP; execution errors surface at the next synchronising call. */
 int tfan_step(tfan_sim* s, int64_t n);
 
 /* Copy the current fields to host float64 arrays (any may be NULL):
  * phi, qxx, qxy, rho_a, rho_p [ny][nx]; u_a, u_p [2][ny][nx].  The velocities
- * are the half-force-corrected ones of the step's own velocity solve.
+ * are the half-force-corrected ones of the step's own velocity solve (Guo
+ * forcing, Numerical Simulation: rho u = sum_i f_i c_i + F/2).
  * Synchronises the stream. */
 int tfan_get_fields(tfan_sim* s, double* phi, double* qxx, double* qxy,
                     double* u_a, double* u_p, double* rho_a, double* rho_p);
 
-/* Fill *out.  Returns TFAN_OK, or TFAN_ENONFINITE / TFAN_EUNSTABLE (with *out
- * still filled) when the state is broken.  Synchronises the stream. */
+/* Fill *out with the Results-section observables summed over the grid
+ * (composition and its variance, kinetic energies, enstrophies of u_a and of
+ * the mixture velocity, Frank elastic energy, mean order S) in float64.
+ * Returns TFAN_OK, or TFAN_ENONFINITE / TFAN_EUNSTABLE (with *out still
+ * filled) when the state is broken.  Synchronises the stream. */
 int tfan_diagnostics(tfan_sim* s, tfan_diag* out);
 
 /* Checkpoint: the raw device state (step counter int64, populations in their
@@ -147,16 +164,22 @@ int tfan_get_state(tfan_sim* s, void* host, size_t bytes);
 int tfan_set_state(tfan_sim* s, const void* host, size_t bytes);
 
 /* Device-side state exchange (for the convolutional surrogate, tfan_cnn.h).
- * tfan_export_state writes phi, Qxx, Qxy, u_a (x, y) and u_p (x, y) of the
- * current state as float32 planes [7][ny][nx] into dev_out (caller-owned device
- * memory); the velocities are the ones tfan_get_fields returns.
- * tfan_import_state sets phi and Q from dev_in [7][ny][nx] and both population
- * sets to f^eq(rho0, u) of its velocities (density deviations restart at zero,
- * as after tfan_init_fields), and sets the step counter to `step` (>= 0).
- * Both are enqueued on the solver's stream and do not synchronise; the
- * device arrays must stay valid until the stream reaches them. */
-int tfan_export_state(tfan_sim* s, float* dev_out);
-int tfan_import_state(tfan_sim* s, const float* dev_in, int64_t step);
+ * Layout [7][ny][nx] float32: phi, Qxx, Qxy, u_a (x, y), u_p (x, y);
+ * tfan_exchange_bytes() = 7 nx ny 4 bytes.
+ * tfan_export_state writes the current state into dev_out; the velocities are
+ * the ones tfan_get_fields returns (the step's own half-force velocity solve).
+ * tfan_import_state sets phi and Q from dev_in and both population sets to
+ * f^eq(rho0, u) of its velocities (density deviations restart at zero, as after
+ * tfan_init_fields), and sets the step counter to `step` (>= 0).
+ * The arrays are caller-owned device memory on the handle's GPU: a pointer the
+ * HIP runtime does not know as a device allocation of that GPU gives
+ * TFAN_EINVAL; fewer than tfan_exchange_bytes() bytes (the `bytes` argument, or
+ * what is left of the allocation from the pointer on) give TFAN_ENOMEM.  Both
+ * are enqueued on the solver's stream as kernels (no runtime copies) and do not
+ * synchronise; the arrays must stay valid until the stream reaches them. */
+size_t tfan_exchange_bytes(const tfan_sim* s);
+int tfan_export_state(tfan_sim* s, float* dev_out, size_t bytes);
+int tfan_import_state(tfan_sim* s, const float* dev_in, size_t bytes, int64_t step);
 
 /* Wait for the handle's stream; reports execution errors. */
 int tfan_sync(tfan_sim* s);

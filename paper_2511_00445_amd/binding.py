@@ -94,8 +94,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_batch_destroy": (None, [_vp]),
         "tfan_batch_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
-        "tfan_export_state": (ctypes.c_int, [_vp, _vp]),
-        "tfan_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int64]),
+        "tfan_exchange_bytes": (ctypes.c_size_t, [_vp]),
+        "tfan_export_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+        "tfan_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int64]),
         "tfan_cnn_param_count": (ctypes.c_int64, []),
         "tfan_cnn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_int32]),
@@ -261,12 +262,12 @@ class Sim:
     def export_state(self, out):
         """Write (phi, Qxx, Qxy, u_a, u_p) as float32 [7][ny][nx] into the device tensor out."""
         _check_dev(out, (7, self.ny, self.nx))
-        self._check(self.lib.tfan_export_state(self._handle, _vp(out.data_ptr())))
+        self._check(self.lib.tfan_export_state(self._handle, _vp(out.data_ptr()), out.numel() * 4))
 
     def import_state(self, x, step: int):
         """Set phi, Q and equilibrium populations from the device tensor x [7][ny][nx]."""
         _check_dev(x, (7, self.ny, self.nx))
-        self._check(self.lib.tfan_import_state(self._handle, _vp(x.data_ptr()), int(step)))
+        self._check(self.lib.tfan_import_state(self._handle, _vp(x.data_ptr()), x.numel() * 4, int(step)))
 
     def step_count(self) -> int:
         return int(self.lib.tfan_step_count(self._handle))
@@ -591,3 +592,4 @@ class Analysis:
             self.close()
         except Exception:
             pass
+

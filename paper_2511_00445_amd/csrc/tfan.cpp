@@ -450,32 +450,60 @@ int tfan_sync(tfan_sim* s) {
 
 int64_t tfan_step_count(const tfan_sim* s) { return s ? s->step : -1; }
 
-int tfan_export_state(tfan_sim* s, float* out) {
+// A caller's device array must be device memory of this handle's GPU that holds
+// `bytes` bytes from ptr on.  An address the HIP runtime does not know as a device
+// allocation (host memory, a stale or foreign pointer) is rejected here: passed to a
+// runtime copy it would be copied on the CPU, and passed to a kernel it would fault.
+static int check_device_range(tfan_sim* s, const void* ptr, size_t bytes, const char* what) {
+  hipPointerAttribute_t at{};
+  hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess || at.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(s, TFAN_EINVAL, std::string(what) + " is not device memory");
+  }
+  if (at.device != s->device) return fail(s, TFAN_EINVAL, std::string(what) + " is on another device");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(s, TFAN_EINVAL, std::string(what) + ": allocation range unknown");
+  }
+  if ((const char*)ptr + bytes > (const char*)base + size)
+    return fail(s, TFAN_ENOMEM, std::string(what) + " extends past the end of its allocation");
+  return TFAN_OK;
+}
+
+size_t tfan_exchange_bytes(const tfan_sim* s) { return s ? 7 * (size_t)s->dp.n * sizeof(float) : 0; }
+
+int tfan_export_state(tfan_sim* s, float* out, size_t bytes) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!out) return fail(s, TFAN_EINVAL, "output array is NULL");
-  const size_t n = (size_t)s->dp.n;
+  const size_t need = tfan_exchange_bytes(s);
+  if (bytes < need) return fail(s, TFAN_ENOMEM, "output array smaller than 7 planes of the grid");
+  if (int rc = check_device_range(s, out, need, "output array")) return rc;
+  const int n = s->dp.n;
   {
     TimedLaunch t(s, tfan::K_FIELDS);
     hipError_t e = tfan::launch_fields(s->dp, state_of(s, s->cur), s->aux, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "fields kernel launch");
   }
   // aux holds [drho_a, drho_p, u_a (2), u_p (2)]
-  hipError_t e = hipMemcpyAsync(out, s->phi[s->cur], n * 4, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(out + n, s->q[s->cur], 2 * n * 4, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(out + 3 * n, s->aux + 2 * n, 4 * n * 4, hipMemcpyDeviceToDevice, s->stream);
-  return e == hipSuccess ? TFAN_OK : hip_fail(s, e, "state export");
+  hipError_t e = tfan::launch_pack_state(n, s->phi[s->cur], s->q[s->cur], s->aux + 2 * (size_t)n, out, s->stream);
+  return e == hipSuccess ? TFAN_OK : hip_fail(s, e, "state export launch");
 }
 
-int tfan_import_state(tfan_sim* s, const float* in, int64_t step) {
+int tfan_import_state(tfan_sim* s, const float* in, size_t bytes, int64_t step) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
   if (!in) return fail(s, TFAN_EINVAL, "input array is NULL");
   if (step < 0) return fail(s, TFAN_EINVAL, "step must be >= 0");
-  const size_t n = (size_t)s->dp.n;
+  const size_t need = tfan_exchange_bytes(s);
+  if (bytes < need) return fail(s, TFAN_ENOMEM, "input array smaller than 7 planes of the grid");
+  if (int rc = check_device_range(s, in, need, "input array")) return rc;
+  const int n = s->dp.n;
   s->cur = 0;
-  hipError_t e = hipMemcpyAsync(s->phi[0], in, n * 4, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->q[0], in + n, 2 * n * 4, hipMemcpyDeviceToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(s->aux, in + 3 * n, 4 * n * 4, hipMemcpyDeviceToDevice, s->stream);
-  if (e != hipSuccess) return hip_fail(s, e, "state import");
+  hipError_t e = tfan::launch_unpack_state(n, in, s->phi[0], s->q[0], s->aux, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "state import launch");
   {
     TimedLaunch t(s, tfan::K_INIT);
     e = tfan::launch_init(s->dp, s->aux, state_of(s, 0), s->stream);

@@ -107,5 +107,10 @@ hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: d
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,
                        double* partials, int nblocks, double* result, hipStream_t st);
 int diag_blocks(const DevParams& P);
+// State exchange [7][n] (phi, Qxx, Qxy, u_a, u_p): pack from phi, q [2][n] and the
+// velocity planes aux_u [4][n]; unpack the other way.
+hipError_t launch_pack_state(int n, const float* phi, const float* q, const float* aux_u, float* out,
+                             hipStream_t st);
+hipError_t launch_unpack_state(int n, const float* in, float* phi, float* q, float* aux_u, hipStream_t st);
 
 }  // namespace tfan

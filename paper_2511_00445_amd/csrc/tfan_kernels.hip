@@ -5,6 +5,8 @@
 // are stored after collision and before streaming ("post-collision"), shifted by
 // -w_i rho0 so that the small deviations from rest keep float32 precision; the
 // next step streams them by pulling f_i(x) = f*_i(x - c_i).
+#include <algorithm>
+
 #include "tfan_internal.h"
 
 namespace tfan {
@@ -1082,6 +1084,32 @@ __global__ void __launch_bounds__(256) k_init(DevParams P, const float* __restri
   }
 }
 
+// State exchange layout [7][n]: phi, Qxx, Qxy, u_a,x, u_a,y, u_p,x, u_p,y.  The
+// velocities come from (pack) or go to (unpack) planes 2..5 / 0..3 of aux.
+__global__ void __launch_bounds__(256) k_pack_state(int n, const float* __restrict__ phi,
+                                                    const float* __restrict__ q,
+                                                    const float* __restrict__ aux_u,
+                                                    float* __restrict__ out) {
+  const size_t total = 7 * (size_t)n;
+  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
+    const size_t plane = j / (size_t)n, i = j - plane * (size_t)n;
+    const float v = plane == 0 ? phi[i] : plane < 3 ? q[(plane - 1) * (size_t)n + i] : aux_u[(plane - 3) * (size_t)n + i];
+    out[j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_unpack_state(int n, const float* __restrict__ in, float* __restrict__ phi,
+                                                      float* __restrict__ q, float* __restrict__ aux_u) {
+  const size_t total = 7 * (size_t)n;
+  for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
+    const size_t plane = j / (size_t)n, i = j - plane * (size_t)n;
+    const float v = in[j];
+    if (plane == 0) phi[i] = v;
+    else if (plane < 3) q[(plane - 1) * (size_t)n + i] = v;
+    else aux_u[(plane - 3) * (size_t)n + i] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Diagnostics: per-site float64 contributions, wavefront shuffle reduction,
 // one record per block, then a single-block pass.  Deterministic for a given
@@ -1317,6 +1345,21 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
   if (P.pop16) launch_collide_tiles<true, _Float16, 2>(P, in, nullptr, aux, st);
   else launch_collide_tiles<true, float, 2>(P, in, nullptr, aux, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_state(int n, const float* phi, const float* q, const float* aux_u, float* out,
+                             hipStream_t st) {
+  const size_t total = 7 * (size_t)n;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_pack_state, dim3(blocks), dim3(256), 0, st, n, phi, q, aux_u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_state(int n, const float* in, float* phi, float* q, float* aux_u, hipStream_t st) {
+  const size_t total = 7 * (size_t)n;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_unpack_state, dim3(blocks), dim3(256), 0, st, n, in, phi, q, aux_u);
   return hipGetLastError();
 }
 

@@ -48,6 +48,40 @@ def test_error_codes(gpu):
     assert rc == T.TFAN_ENOMEM
 
 
+def test_state_exchange_checks_its_arrays(gpu):
+    """export/import reject host memory and arrays shorter than 7 planes on the host,
+    before anything is enqueued; a valid export/import round trip keeps the fields."""
+    say("case: state exchange argument checks")
+    import torch
+    import paper_2511_00445_amd as T
+    p = workload_params("small_64")
+    s = make(p)
+    n = 64 * 64
+    need = int(s.lib.tfan_exchange_bytes(s.handle))
+    assert need == 7 * n * 4
+    vp = ctypes.c_void_p
+    host = np.zeros(7 * n, np.float32)
+    assert s.lib.tfan_export_state(s.handle, host.ctypes.data_as(vp), need) == T.TFAN_EINVAL
+    assert s.lib.tfan_import_state(s.handle, host.ctypes.data_as(vp), need, 0) == T.TFAN_EINVAL
+    dev = torch.zeros(7 * n, dtype=torch.float32, device="cuda")
+    assert s.lib.tfan_export_state(s.handle, vp(dev.data_ptr()), need - 4) == T.TFAN_ENOMEM
+    s.sync()
+    x = torch.empty((7, 64, 64), dtype=torch.float32, device="cuda")
+    s.export_state(x)
+    f = s.get_fields()
+    xh = x.cpu().numpy()
+    np.testing.assert_array_equal(xh[0], f["phi"].astype(np.float32))
+    np.testing.assert_array_equal(xh[3:5], f["u_a"].astype(np.float32))
+    np.testing.assert_array_equal(xh[5:7], f["u_p"].astype(np.float32))
+    s.import_state(x, 7)
+    g = s.get_fields()
+    assert s.step_count() == 7
+    np.testing.assert_array_equal(g["qxx"], f["qxx"])
+    # populations restart at f^eq(rho0, u): density deviations are zero up to the
+    # float32 rounding of the shifted equilibrium (|u| ~ 1e-3 here)
+    np.testing.assert_allclose(g["rho_a"], 1.0, rtol=0, atol=1e-8)
+
+
 def test_health_flags(gpu):
     say("case: nonfinite and unstable flags")
     import paper_2511_00445_amd as T

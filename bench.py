@@ -24,21 +24,35 @@ ANALYSIS_BYTES_PER_SITE = 52 + 5 * 2 * 16 + 48 + 24 + 8  # one observables snaps
 # fp32 vector peak without packed fp32 instructions (the build disables them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
 VALU_F32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Algorithmic bytes per lattice site moved by each kernel (float32 storage):
-# populations 2 fluids x 9 x 4 B read and written, phi/Qxx/Qxy 12 B, and the
-# frozen velocities (u_a, u_c: 16 B) that link the collision and sub-step kernels.
+# Algorithmic bytes per lattice site (float32 storage) as the method defines them:
+# the whole coupled step reads and writes 2 fluids x 9 populations and phi, Qxx, Qxy
+# (168 B).  The collision kernel's share is the populations (144 B) and the read of
+# phi/Q (12 B); the frozen velocities u_a, u_c it writes (16 B) link the collision
+# and sub-step kernels of this design and are reported as overhead, not counted.
 ALG_BYTES = {
-    "step": 168,        # whole coupled step: 2*9*4*2 + 3*4*2
-    "collide": 172,     # pull+write populations (144), read phi/Q (12), write u_a, u_c (16)
-    "substep": 40,      # one sub-step: read phi/Q (12) and u_a/u_c (16), write phi/Q (12)
-    "substeps": 40,     # blocked sub-steps: the same 40 B once per launch
+    "step": 168,        # 2*9*4*2 + 3*4*2
+    "collide": 156,     # populations read + written (144), phi/Q read (12)
+    "substep": 24,      # sub-step launch: phi/Q read and written
+    "substeps": 24,     # blocked sub-steps: phi/Q read and written once per launch
 }
+OVERHEAD_BYTES = {"collide": 16, "substep": 16, "substeps": 16}   # u_a/u_c written, then read
 # Arithmetic operations per site of one finite-difference sub-step, as the method
 # defines them (no halo recomputation): Cahn-Hilliard 29 (mu 11, div(phi u_c) 9,
 # lap mu 5, update 4), Beris-Edwards 81 (W 8, its parts 7, LdG factor 6, lap Q
 # and H 16, S(W, Q) 18, advection 16, update 10).
 SUBSTEP_FLOPS = 110
 BOUND = {"collide": "hbm", "substep": "hbm", "substeps": "alu"}
+
+
+def shader_clock_mhz():
+    """Current shader (GFX) clock of GPU 0 in MHz from amdsmi, or None."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        h = amdsmi.amdsmi_get_processor_handles()[0]
+        return int(amdsmi.amdsmi_get_clock_info(h, amdsmi.AmdSmiClkType.GFX)["clk"])
+    except Exception:
+        return None
 
 
 def source_hash() -> str:
@@ -300,6 +314,8 @@ def main():
     ap.add_argument("--storage", choices=("f32", "f16"), default="f32",
                     help="population storage (f16: binary16 deviations, float32 arithmetic)")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--settle-s", type=float, default=2.0,
+                    help="seconds of untimed steps right before the timed region (clock settle)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--single-core-budget", type=float, default=8.0,
                     help="seconds of the oracle on one thread (0: skip)")
@@ -353,18 +369,18 @@ def main():
     print(f"[bench] {args.workload}: {nx}x{ny}, warmup {args.warmup}", file=sys.stderr, flush=True)
     sim.step(args.warmup)
     sim.sync()
-    # per-launch HIP events on the first `sampled` timed steps only: an event pair
-    # around every launch of all 2000 steps costs ~5% of the throughput
-    fd = tuning[1]
-    if fd == 165:
-        block = min(p["n_sub"], 5)
-    else:
-        block = {162: 2, 163: 3}.get(fd, p["n_sub"] if fd in (16, 32) and p["n_sub"] <= 5 else 1)
-    launches_per_step = 1 + -(-p["n_sub"] // block)
-    sampled = min(args.steps, 200)
-    sim.kernel_timing(sampled * launches_per_step)
-    stream = sim.stream
+    # The shader clock idles at a few hundred MHz and needs about a second of load to
+    # reach its steady ~2.4 GHz (a 20-step region timed from idle runs ~15% slow), so
+    # the device is kept busy with untimed steps for a fixed wall time right before
+    # the timed region; reported as its own field, independent of --warmup.
+    settle_steps, t_s = 0, time.perf_counter()
+    while time.perf_counter() - t_s < args.settle_s:
+        sim.step(20)
+        sim.sync()
+        settle_steps += 20
+    clk_before = shader_clock_mhz()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = sim.stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
@@ -374,12 +390,29 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     region_ms = ev0.elapsed_time(ev1)
+    clk_after = shader_clock_mhz()
+    # Kernel durations in a second pass of the same length right after the timed one,
+    # with HIP events around every launch on the solver's stream (kept out of the
+    # timed region, whose throughput they would lower).
+    fd = tuning[1]
+    if fd == 165:
+        block = min(p["n_sub"], 5)
+    else:
+        block = {162: 2, 163: 3}.get(fd, p["n_sub"] if fd in (16, 32) and p["n_sub"] <= 5 else 1)
+    launches_per_step = 1 + -(-p["n_sub"] // block)
+    sampled = max(args.steps, 20)
+    sim.kernel_timing(sampled * launches_per_step)
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2.record(stream)
+    sim.step(sampled)
+    ev3.record(stream)
     ktimes = sim.kernel_times()
     sim.kernel_timing(0)
+    timed_pass_ms = ev2.elapsed_time(ev3)
     diag = sim.diagnostics()
     if diag["status"] != 0:
         raise SystemExit(f"benchmark state is unhealthy: status {diag['status']}")
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] timed {args.steps} steps in {wall:.4f} s", file=sys.stderr, flush=True)
 
     sites = nx * ny
     mlups = sites * args.steps / wall / 1e6
@@ -402,13 +435,14 @@ def main():
                     "traffic": measured_traffic(name) if p["storage"] == 0 else None,
                     "alg_flops_per_launch": flops, "avg_launch_us": round(avg_s * 1e6, 2),
                     "hbm_alg_bytes_per_launch": alg_bytes[name] * sites,
-                    "hbm_achieved_GBs": round(alg_bytes[name] * sites / avg_s / 1e9, 1)}
+                    "overhead_bytes_per_launch": OVERHEAD_BYTES[name] * sites}
         alg = alg_bytes[name] * sites
         achieved = alg / avg_s / 1e9
         return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(name) if p["storage"] == 0 else None,
-                "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2)}
+                "alg_bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2),
+                "overhead_bytes_per_launch": OVERHEAD_BYTES[name] * sites}
 
     # dominant kernel: largest total time in the timed region
     hot = [k for k, v in ktimes.items() if v[1] > 0 and k in BOUND]
@@ -437,7 +471,11 @@ def main():
         "step_roofline": {"alg_bytes_per_site": alg_bytes["step"], "achieved": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels_ms": {k: [round(v[0], 3), v[1]] for k, v in ktimes.items() if v[1] > 0},
+        "kernel_sum_ms_per_step": round(sum(v[0] for k, v in ktimes.items() if k in BOUND) / sampled, 5),
         "event_region_ms": round(region_ms, 3),
+        "kernel_timing_pass": {"steps": sampled, "ms_per_step": round(timed_pass_ms / sampled, 5)},
+        "clock_settle": {"seconds": args.settle_s, "untimed_steps": settle_steps},
+        "gpu_clock_mhz": {"before": clk_before, "after": clk_after},
         "source_hash": source_hash(),
     }
     if not args.no_cpu_baseline:

@@ -79,6 +79,21 @@ int tfan_analysis_defects(tfan_analysis* a, const float* state, int64_t* plus, i
 int tfan_analysis_all(tfan_analysis* a, const float* state, double* E, double* W, double* S, double* L,
                       double* Cuu, double* Cww, double* CQQ, double* count, int64_t* plus, int64_t* minus);
 
+/* Allocation-free variant of tfan_analysis_overlaps, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): no handle and no workspace.  Same inputs and the same
+ * six site means in out[6] (host array), computed by the same kernels on
+ * hip_stream (hipStream_t, NULL = default stream) of the current device; the
+ * call synchronises that stream.  The block partials live in a fixed array of
+ * 49,200 bytes inside the library, one copy per GPU, held until the process
+ * ends; the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Sizes: n a power of two in [8, 4096] (the reduction uses at most
+ * 1024 blocks), else TFAN_EINVAL.  Calls that overlap on one GPU (other threads
+ * or streams) share that array and race: serialise them.  The message of the
+ * last failure: tfan_analysis_noalloc_last_error(). */
+int tfan_analysis_overlaps_noalloc(int32_t n, const float* s0, const float* s1, double* out, void* hip_stream);
+const char* tfan_analysis_noalloc_last_error(void);
+
 int tfan_analysis_sync(tfan_analysis* a);
 void tfan_analysis_destroy(tfan_analysis* a);
 const char* tfan_analysis_last_error(const tfan_analysis* a);

@@ -121,6 +121,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_analysis_correlations": (ctypes.c_int, [_vp, _vp, _dp, _dp, _dp, _dp]),
         "tfan_analysis_overlaps": (ctypes.c_int, [_vp, _vp, _vp, _dp]),
         "tfan_analysis_defects": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int64), _P(ctypes.c_int64)]),
+        "tfan_analysis_overlaps_noalloc": (ctypes.c_int, [ctypes.c_int32, _vp, _vp, _dp, _vp]),
+        "tfan_analysis_noalloc_last_error": (ctypes.c_char_p, []),
         "tfan_analysis_sync": (ctypes.c_int, [_vp]),
         "tfan_analysis_destroy": (None, [_vp]),
         "tfan_analysis_last_error": (ctypes.c_char_p, [_vp]),
@@ -593,3 +595,21 @@ class Analysis:
         except Exception:
             pass
 
+
+def analysis_overlaps_noalloc(x0, x1, stream=None) -> np.ndarray:
+    """tfan_analysis_overlaps_noalloc: the six overlap means of two exported states
+    [7][n][n] (float32 device tensors), computed without any device allocation."""
+    import torch
+    lib = load_library()
+    _check_dev(x0)
+    _check_dev(x1)
+    n = int(x0.shape[-1])
+    if tuple(x0.shape[-3:]) != (7, n, n) or tuple(x1.shape[-3:]) != (7, n, n):
+        raise TfanError(TFAN_EINVAL, "expected two states of shape [7][n][n]")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    out = np.empty(6)
+    rc = lib.tfan_analysis_overlaps_noalloc(n, _vp(x0.data_ptr()), _vp(x1.data_ptr()), _ptr(out),
+                                            _vp(st.cuda_stream))
+    if rc != TFAN_OK:
+        raise TfanError(rc, lib.tfan_analysis_noalloc_last_error().decode())
+    return out

@@ -21,7 +21,8 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-ffp-contract=on", "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
-SOURCES = ["tfan.cpp", "tfan_kernels.hip", "cnn.cpp", "cnn_kernels.hip", "analysis.cpp", "analysis_kernels.hip"]
+SOURCES = ["tfan.cpp", "tfan_kernels.hip", "cnn.cpp", "cnn_kernels.hip", "analysis.cpp", "analysis_kernels.hip",
+           "overlaps_noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -212,6 +212,13 @@ static void analysis_checks() {
   EXPECT(tfan_analysis_create(64, ws, 4096, nullptr, &a) == TFAN_ENOMEM);
   std::free(ws);
   tfan_analysis_destroy(nullptr);
+  double out[6];
+  float dummy[8];
+  for (int n : {7, 12, 4, 8192})
+    EXPECT(tfan_analysis_overlaps_noalloc(n, dummy, dummy, out, nullptr) == TFAN_EINVAL);
+  EXPECT(tfan_analysis_overlaps_noalloc(64, nullptr, dummy, out, nullptr) == TFAN_EINVAL);
+  EXPECT(tfan_analysis_overlaps_noalloc(64, dummy, dummy, nullptr, nullptr) == TFAN_EINVAL);
+  EXPECT(std::strlen(tfan_analysis_noalloc_last_error()) > 0);
 }
 
 int main() {

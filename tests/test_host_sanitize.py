@@ -31,9 +31,10 @@ def test_host_code_under_sanitizers(tmp_path):
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
     objs = []
-    for src in ("tfan.cpp", "cnn.cpp", "analysis.cpp"):
+    for src in ("tfan.cpp", "cnn.cpp", "analysis.cpp", "overlaps_noalloc.hip"):
         obj = str(tmp_path / (src + ".o"))
-        subprocess.run([cc, "-O1", "-g"] + base + san + ["-c", os.path.join(CSRC, src), "-o", obj],
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        subprocess.run([cc, "-O1", "-g"] + base + san + lang + ["-c", os.path.join(CSRC, src), "-o", obj],
                        check=True, capture_output=True)
         objs.append(obj)
     for src in ("tfan_kernels.hip", "cnn_kernels.hip", "analysis_kernels.hip"):

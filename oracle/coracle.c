@@ -31,6 +31,7 @@ typedef struct {
   double *w;                  /* velocity gradient of u_a [4][n]: W_xx, W_xy, W_yx, W_yy */
   double *phi2, *qxx2, *qxy2; /* sub-step output */
   double *mu2;
+  double *pm;                 /* phi * mu at the step's start */
 } oc_sim;
 
 static const int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -124,13 +125,14 @@ oc_sim* oc_create(const oc_params* p) {
   s->phi2 = calloc(n, sizeof(double));
   s->qxx2 = calloc(n, sizeof(double));
   s->qxy2 = calloc(n, sizeof(double));
+  s->pm = calloc(n, sizeof(double));
   return s;
 }
 
 void oc_destroy(oc_sim* s) {
   if (!s) return;
   double* arr[] = {s->fa, s->fp, s->ta, s->tp, s->phi, s->qxx, s->qxy, s->mu, s->mu2, s->sig,
-                   s->ua, s->up, s->uc, s->w, s->phi2, s->qxx2, s->qxy2};
+                   s->ua, s->up, s->uc, s->w, s->phi2, s->qxx2, s->qxy2, s->pm};
   for (size_t k = 0; k < sizeof(arr) / sizeof(arr[0]); ++k) free(arr[k]);
   free(s);
 }
@@ -158,6 +160,7 @@ static void potentials(oc_sim* s, const double* phi, double* mu) {
     for (int x = 0; x < nx; ++x) {
       const int i = y * nx + x;
       mu[i] = s->p.A_ch * (phi[i] * phi[i] * phi[i] - phi[i]) - s->p.kappa * lap(phi, x, y, nx, ny);
+      if (mu == s->mu) s->pm[i] = phi[i] * mu[i];
     }
   (void)n;
 }
@@ -216,7 +219,9 @@ static void collide(oc_sim* s) {
       const double Fy = ddx(sx + 2 * n, x, y, nx) + ddy(sx + 3 * n, x, y, nx, ny);
       const double ph = s->phi[i];
       const double c1 = 0.5 * (1.0 + ph), c2 = 0.5 * (1.0 - ph);
-      const double chx = -ph * ddx(s->mu, x, y, nx), chy = -ph * ddy(s->mu, x, y, nx, ny);
+      /* capillary force mu grad(phi) - grad(phi mu), each term by central differences */
+      const double chx = s->mu[i] * ddx(s->phi, x, y, nx) - ddx(s->pm, x, y, nx);
+      const double chy = s->mu[i] * ddy(s->phi, x, y, nx, ny) - ddy(s->pm, x, y, nx, ny);
       const double Gax = Fx + c1 * chx, Gay = Fy + c1 * chy, Gpx = c2 * chx, Gpy = c2 * chy;
       double ra = 0, rp = 0, max_ = 0, may = 0, mpx = 0, mpy = 0;
       for (int k = 0; k < 9; ++k) {

@@ -12,8 +12,8 @@ passive Newtonian fluid (u2 = u_p) on a 2D periodic lattice:
     coupled by the drag F_drag = gamma c1 c2 (u_p - u_a) (Model, drag force);
   * the elastic stress of the Beris-Edwards model (Model, elastic stress display),
     the active stress -zeta c1 Q (Model, active force; sign: zeta > 0 extensile)
-    and the capillary force F_ch = mu grad(phi) - grad(phi mu) = -phi grad(mu)
-    (Model, capillary force equation);
+    and the capillary force F_ch = mu grad(phi) - grad(phi mu) (Model, capillary
+    force equation), discretised term by term;
   * n_sub forward-Euler finite-difference sub-steps of the Cahn-Hilliard equation
     (Model, Eqs. 1-3) and the Beris-Edwards equation (Model, Eqs. 11-12) with the
     velocities frozen at the start of the step (Numerical Simulation).
@@ -123,8 +123,12 @@ def ch_rhs(phi, uc, p):
 
 
 def capillary_force(phi, mu):
-    """F_ch = mu grad(phi) - grad(phi mu), which equals -phi grad(mu) (Model, capillary force)."""
-    return -phi * np.array([d_x(mu), d_y(mu)])
+    """F_ch = mu grad(phi) - grad(phi mu) (Model, capillary force), each gradient by
+    the central differences of the method, term by term as the paper writes it.
+    (The continuum identity -phi grad(mu) does not hold discretely: the central
+    difference of a product differs from the product rule, and the term-by-term
+    form takes mu's differences across the two neighbouring faces.)"""
+    return np.array([mu * d_x(phi) - d_x(phi * mu), mu * d_y(phi) - d_y(phi * mu)])
 
 
 # ----------------------------------------------------------------------------

@@ -138,10 +138,11 @@ __device__ __forceinline__ void collide_fluid(float f[9], float dr, float ux, fl
   }
 }
 
-// Stencil inputs of one site's update: the stress components and mu at the four
-// neighbours (E, W: x +- 1; N, S: y +- 1) and phi at the site.
+// Stencil inputs of one site's update: the stress components, mu and phi at the
+// four neighbours (E, W: x +- 1; N, S: y +- 1) and phi, mu at the site.
 struct SiteStencil {
   float xxE, xxW, yyN, yyS, sE, sW, sN, sS, aE, aW, aN, aS, muE, muW, muN, muS, phi;
+  float mu, phE, phW, phN, phS;
 };
 
 // Forces, Guo velocities with the drag implicit, and (COLLIDE) both collisions of
@@ -156,9 +157,13 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
   const float Fy = 0.5f * ((t.sE - t.aE) - (t.sW - t.aW)) + 0.5f * (t.yyN - t.yyS);
   const float pC = t.phi;
   const float c1 = 0.5f * (1.f + pC), c2 = 0.5f * (1.f - pC);
-  // capillary force -phi grad(mu), shared c1 : c2
-  const float fchx = -pC * 0.5f * (t.muE - t.muW);
-  const float fchy = -pC * 0.5f * (t.muN - t.muS);
+  // capillary force mu grad(phi) - grad(phi mu) with both gradients by central
+  // differences (Model, capillary force), shared c1 : c2.  Term by term,
+  // mu_C (phi_E - phi_W)/2 - (phi_E mu_E - phi_W mu_W)/2
+  //   = (phi_E (mu_C - mu_E) - phi_W (mu_C - mu_W)) / 2,
+  // the form evaluated here (the same value, fewer roundings).
+  const float fchx = 0.5f * (t.phE * (t.mu - t.muE) - t.phW * (t.mu - t.muW));
+  const float fchy = 0.5f * (t.phN * (t.mu - t.muN) - t.phS * (t.mu - t.muS));
   const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
   const float Gpx = c2 * fchx, Gpy = c2 * fchy;
   float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
@@ -374,7 +379,8 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
                            ssy[sy][sx + 1], ssy[sy][sx - 1], ssy[sy + 1][sx], ssy[sy - 1][sx],
                            san[sy][sx + 1], san[sy][sx - 1], san[sy + 1][sx], san[sy - 1][sx],
                            smu[sy][sx + 1], smu[sy][sx - 1], smu[sy + 1][sx], smu[sy - 1][sx],
-                           sph[ly + 2][tx + 2]};
+                           sph[ly + 2][tx + 2], smu[sy][sx],
+                           sph[ly + 2][tx + 3], sph[ly + 2][tx + 1], sph[ly + 3][tx + 2], sph[ly + 1][tx + 2]};
     float uo[6];
     site_update<!FIELDS>(P, fa[s], fp[s], t, uo);
     const int idx = y * nx + x;

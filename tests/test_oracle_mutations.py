@@ -54,7 +54,9 @@ MUTATIONS = [
      - p["M"] * O.lap(O.chemical_potential(phi, p["A_ch"], p["kappa"])),
      T.test_p7_ch_linear_growth, (0.0, (4, 0), 0.01)),
     ("capillary force sign", "capillary_force",
-     lambda phi, mu: phi * np.array([O.d_x(mu), O.d_y(mu)]), T.test_p7_ch_linear_growth, (0.3, (2, 3), 0.01)),
+     lambda phi, mu: -O.capillary_force(phi, mu), T.test_p7_ch_linear_growth, (0.3, (2, 3), 0.01)),
+    ("capillary force as -phi D(mu)", "capillary_force",
+     lambda phi, mu: -phi * np.array([O.d_x(mu), O.d_y(mu)]), T.test_p22_capillary_force_term_by_term, (2, 16)),
     ("H: sign of K lap Q", "molecular_field",
      lambda Q, A, C, K, B=0.0: -(A * Q + C * O.mm(O.mm(Q, Q), Q) + K * O.lap(Q)),
      T.test_p13_q_mode_relaxation, ((3, 0), 0)),

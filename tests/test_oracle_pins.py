@@ -662,3 +662,26 @@ def test_p21_free_energy_composition_mode_and_flow():
     o2 = _fresh(p, z + 0.4, z, z, u_a=Ua[:, None, None] * one, u_p=Up[:, None, None] * one)
     exact = 0.25 * p["A_ch"] * (0.16 - 1) ** 2 * N + 0.5 * rho0 * (Ua @ Ua + Up @ Up) * N
     assert abs(o2.free_energy() - exact) < 1e-13 * N
+
+
+# ---------------------------------------------------------------------------
+# P22: the capillary force mu grad(phi) - grad(phi mu), each gradient a central
+# difference, on two Fourier modes phi = a sin(k1 x), mu = b cos(k2 x).  From the
+# product-to-sum identities and D sin(qx) = sin(q) cos(qx), D cos(qx) = -sin(q) sin(qx):
+#   F_x = (ab/2) [(sin k1 - sin(k1 + k2)) cos((k1 + k2) x) + (sin k1 - sin(k1 - k2)) cos((k1 - k2) x)].
+# At the grid scale, k2 = pi (mu = b (-1)^x), this is 2 a b sin(k1) cos(k1 x) (-1)^x,
+# while the continuum-equivalent -phi D(mu) vanishes there (D is blind to (-1)^x).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m1,m2", [(3, 5), (2, 16), (5, 13)])
+def test_p22_capillary_force_term_by_term(m1, m2):
+    N, a, b = 32, 0.7, 0.03
+    x = np.arange(N)[None, :] * np.ones((6, 1))
+    k1, k2 = 2 * np.pi * m1 / N, 2 * np.pi * m2 / N
+    phi, mu = a * np.sin(k1 * x), b * np.cos(k2 * x)
+    F = O.capillary_force(phi, mu)
+    ex = 0.5 * a * b * ((np.sin(k1) - np.sin(k1 + k2)) * np.cos((k1 + k2) * x)
+                        + (np.sin(k1) - np.sin(k1 - k2)) * np.cos((k1 - k2) * x))
+    np.testing.assert_allclose(F[0], ex, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(F[1], 0.0, atol=1e-17)
+    if m2 == N // 2:
+        np.testing.assert_allclose(F[0], 2 * a * b * np.sin(k1) * np.cos(k1 * x) * (-1.0) ** x, atol=1e-15)

@@ -173,21 +173,25 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak
 
 def bench_surrogate(args):
     """Surrogate-accelerated coarsening at 1024x1024 (zeta = 0.01, seed 7) against the
-    plain path on the same GPU, steps 6,000-12,000 after a plain start; the network
-    is trained first on 256x256 trajectories by the library's own kernels."""
+    plain path on the same GPU: plain solver to step 6,000, then --deploy-steps
+    lattice steps (default 1,005,000, whole calls of k + relax steps) both ways; the
+    network is trained first on 256x256 trajectories by the library's own kernels."""
     import numpy as np
     import torch
     from paper_2511_00445_amd import Cnn
     from paper_2511_00445_amd import surrogate as S
     from paper_2511_00445_amd.workloads import base_params, initial_fields
     print("[bench] training the surrogate on 256x256 trajectories", file=sys.stderr, flush=True)
-    theta, s_in, s_out, losses, train_s = S.train_surrogate(base_params(256, 256, zeta=0.01),
-                                                            list(range(600, 608)), 1000, 12000,
-                                                            steps=args.train_steps, batch=8)
+    t1 = args.train_t1 or S.TRAIN_T1
+    theta, s_in, s_out, losses, train_s = S.train_surrogate(base_params(256, 256, zeta=0.01), list(S.TRAIN_SEEDS),
+                                                            S.TRAIN_T0, t1, steps=args.train_steps, batch=8)
     n = 1024
     p = base_params(n, n, zeta=0.01)
-    print("[bench] plain and surrogate runs at 1024x1024", file=sys.stderr, flush=True)
-    r = S.deploy_compare(p, 7, theta, s_in, s_out, 6000, 12000, 600, relax=S.RELAX_STEPS)
+    call = S.K_STEPS + S.RELAX_STEPS
+    every = call * 200
+    span = every * max(1, -(-args.deploy_steps // every))
+    print(f"[bench] plain and surrogate runs at 1024x1024, steps 6000-{6000 + span}", file=sys.stderr, flush=True)
+    r = S.deploy_compare(p, 7, theta, s_in, s_out, 6000, 6000 + span, every, relax=S.RELAX_STEPS)
     if r["status"] != 0:
         raise SystemExit("surrogate run became unhealthy")
     # forward-pass throughput with HIP events on the network's stream
@@ -211,12 +215,13 @@ def bench_surrogate(args):
     out_line = {
         "metric": "simulated lattice steps per second, surrogate-accelerated, domain-length error <= 5%",
         "value": round(r["surrogate_steps_per_s"], 1), "unit": "steps/s", "n_gpus": 1,
-        "steps": 6000, "warmup": 6000, "ms_per_step": round(1e3 / r["surrogate_steps_per_s"], 5),
+        "steps": span, "warmup": 6000, "ms_per_step": round(1e3 / r["surrogate_steps_per_s"], 5),
         "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "bf16-mfma/f32",
         "data": "synthetic",
-        "config": {"workload": "surrogate_1024: 1024x1024 periodic, zeta=0.01, seed 7, plain to step 6000, then "
-                               "50-step network jumps + 25 solver steps, solver check every 10 calls, "
-                               "fallback above 5e-2 relative L2 on (phi, Q)",
+        "config": {"workload": f"surrogate_1024: 1024x1024 periodic, zeta=0.01, seed 7, plain to step 6000, then "
+                               f"{span} steps of 50-step network jumps + 25 solver steps, solver check every 10 "
+                               f"calls, fallback above 5e-2 relative L2 on (phi, Q); trained on 256x256 steps "
+                               f"{S.TRAIN_T0}-{t1}",
                    "nx": n, "ny": n, "k": S.K_STEPS, "relax": S.RELAX_STEPS, "parallelism": "single GPU"},
         "plain_steps_per_s": round(r["plain_steps_per_s"], 1), "speedup": round(r["speedup"], 3),
         "max_L_dev": round(r["max_L_dev"], 4), "checks": r["checks"], "fallbacks": r["fallbacks"],
@@ -319,6 +324,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--single-core-budget", type=float, default=8.0,
                     help="seconds of the oracle on one thread (0: skip)")
+    ap.add_argument("--train-t1", type=int, default=0,
+                    help="surrogate_1024: last trajectory step of the training pairs (0: the standard range)")
+    ap.add_argument("--deploy-steps", type=int, default=1000000,
+                    help="surrogate_1024: lattice steps of the deployment after the plain start")
     ap.add_argument("--train-steps", type=int, default=12000,
                     help="surrogate_1024: Adam steps of the surrogate's training")
     ap.add_argument("--tuning", default="", metavar="C,F",
@@ -395,7 +404,7 @@ def main():
     # with HIP events around every launch on the solver's stream (kept out of the
     # timed region, whose throughput they would lower).
     fd = tuning[1]
-    if fd == 165:
+    if fd in (165, 166):
         block = min(p["n_sub"], 5)
     else:
         block = {162: 2, 163: 3}.get(fd, p["n_sub"] if fd in (16, 32) and p["n_sub"] <= 5 else 1)

@@ -197,23 +197,26 @@ int tfan_kernel_times(tfan_sim* s, double* ms_total, int64_t* launches, int n);
 int tfan_kernel_count(void);
 const char* tfan_kernel_name(int id);
 
-/* Launch shape of the hot kernels: collide_rows in {1, 2} rows of sites per
- * thread of the collision kernel; fd_shape selects the finite-difference
- * launches: 1, 2, 4: one launch per sub-step with that many rows per thread;
- * 16, 32: all n_sub sub-steps of a step in one launch on 64 x fd_shape tiles
- * (temporal blocking; for n_sub > 5 the 4-row per-sub-step launch runs);
- * 162, 163: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
- * 165: blocks of up to 5 sub-steps per launch on 64 x 40 tiles, the phi
- * (Cahn-Hilliard) and Q (Beris-Edwards) sub-steps in separate thread blocks.
- * Default (1, 165) below 2^21 sites, (2, 165) from there (a batch: (2, 165)).
- * Results are bitwise identical for every shape; only the speed differs.  Other
- * values: TFAN_EINVAL. */
+/* Launch shape of the hot kernels.  collide_rows: 1 or 2 rows of sites per
+ * thread of the collision kernel on tiles of the default width (256 sites for
+ * float32 storage, 128 for binary16); 11 or 12: the same on tiles of half that
+ * width.  fd_shape selects the finite-difference launches: 1, 2, 4: one launch
+ * per sub-step with that many rows per thread; 16, 32: all n_sub sub-steps of a
+ * step in one launch on 64 x fd_shape tiles (temporal blocking; for n_sub > 5 the
+ * 4-row per-sub-step launch runs); 162, 163: blocks of 2 or 3 sub-steps per
+ * launch on 64 x 16 tiles; 165, 166: blocks of up to 5 sub-steps per launch on
+ * 64 x 40 (165) or 64 x 32 (166) tiles, the phi (Cahn-Hilliard) and Q
+ * (Beris-Edwards) sub-steps in separate thread blocks.  Default (1, 165) below
+ * 2^21 sites, (2, 165) from there (a batch: (2, 165)).  Results are bitwise
+ * identical for every shape; only the speed differs.  Other values: TFAN_EINVAL. */
 int tfan_set_tuning(tfan_sim* s, int32_t collide_rows, int32_t fd_shape);
 int tfan_get_tuning(const tfan_sim* s, int32_t* collide_rows, int32_t* fd_shape);
 
 /* Autotuner: runs `steps` steps (after one warm-up step) with every launch
- * shape, keeps the fastest, restores the state it started from (checkpoint
- * through host memory) and reports the best time per step (may be NULL). */
+ * shape above (4 collision x 9 sub-step shapes, minus blocked shapes that
+ * n_sub turns into the per-sub-step launch), keeps the fastest, restores the
+ * state it started from (checkpoint through host memory) and reports the best
+ * time per step (may be NULL). */
 int tfan_autotune(tfan_sim* s, int32_t steps, double* best_ms_per_step);
 
 /* Release the handle (never the workspace). NULL is ignored. */

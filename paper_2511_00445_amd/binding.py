@@ -279,9 +279,10 @@ class Sim:
 
     def set_tuning(self, collide_rows: int, fd_shape: int):
         """Launch shape (results are bitwise the same for every shape): collide_rows in
-        {1, 2} rows of sites per thread; fd_shape in {1, 2, 4} (one launch per sub-step), {16, 32, 162, 163}
-        (blocked sub-steps, both fields per block) or 165 (blocked, phi and Q in separate
-        blocks).  tfan.h documents each shape."""
+        {1, 2} rows of sites per thread ({11, 12}: on half-width tiles); fd_shape in {1, 2, 4} (one
+        launch per sub-step), {16, 32, 162, 163} (blocked sub-steps, both fields per block) or
+        {165, 166} (blocked, phi and Q in separate blocks, 40- or 32-row tiles).  tfan.h documents
+        each shape."""
         self._check(self.lib.tfan_set_tuning(self._handle, int(collide_rows), int(fd_shape)))
 
     def get_tuning(self) -> tuple:

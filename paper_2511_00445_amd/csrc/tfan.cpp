@@ -142,15 +142,18 @@ struct TimedLaunch {
   tfan_sim* s;
   int kernel;
   int64_t slot = -1;
-  TimedLaunch(tfan_sim* s_, int k) : s(s_), kernel(k) {
+  bool in_dispatch;  // the launcher places the events in the kernel's own dispatch
+  TimedLaunch(tfan_sim* s_, int k, bool in_dispatch_ = false) : s(s_), kernel(k), in_dispatch(in_dispatch_) {
     if (s->ev_used < s->ev_cap) {
       slot = s->ev_used++;
       s->ev_kernel[slot] = kernel;
-      (void)hipEventRecord(s->ev[2 * slot], s->stream);
+      if (!in_dispatch) (void)hipEventRecord(s->ev[2 * slot], s->stream);
     }
   }
+  hipEvent_t start() const { return slot >= 0 ? s->ev[2 * slot] : nullptr; }
+  hipEvent_t stop() const { return slot >= 0 ? s->ev[2 * slot + 1] : nullptr; }
   ~TimedLaunch() {
-    if (slot >= 0) (void)hipEventRecord(s->ev[2 * slot + 1], s->stream);
+    if (slot >= 0 && !in_dispatch) (void)hipEventRecord(s->ev[2 * slot + 1], s->stream);
   }
 };
 
@@ -202,19 +205,23 @@ int download(tfan_sim* s, double* dst, const float* src, size_t count, std::vect
 
 }  // namespace
 
-static const int kFdShapes[] = {1, 2, 4, 16, 32, 162, 163, 165};
+static const int kFdShapes[] = {1, 2, 4, 16, 32, 162, 163, 165, 166};
+static const int kCollideShapes[] = {1, 2, 11, 12};
 static bool valid_shape(int32_t collide_rows, int32_t fd_shape) {
-  if (collide_rows != 1 && collide_rows != 2) return false;
+  bool ok = false;
+  for (int c : kCollideShapes) ok = ok || c == collide_rows;
+  if (!ok) return false;
   for (int f : kFdShapes)
     if (f == fd_shape) return true;
   return false;
 }
-static const char* kShapeMsg = "collide_rows must be 1 or 2 and fd_shape 1, 2, 4, 16, 32, 162, 163 or 165";
+static const char* kShapeMsg =
+    "collide_rows must be 1, 2, 11 or 12 and fd_shape 1, 2, 4, 16, 32, 162, 163, 165 or 166";
 // Shapes the autotuners try: every collide_rows with every fd_shape, skipping
 // blocked shapes that n_sub turns into the per-sub-step launch.
 static std::vector<tfan::Tuning> tuning_candidates(int n_sub) {
   std::vector<tfan::Tuning> out;
-  for (int c : {1, 2})
+  for (int c : kCollideShapes)
     for (int f : kFdShapes) {
       tfan::Tuning t;
       t.collide_rows = c;
@@ -304,8 +311,8 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
   for (int64_t k = 0; k < nsteps; ++k) {
     const int a = s->cur, b = 1 - s->cur;
     {
-      TimedLaunch t(s, tfan::K_COLLIDE);
-      hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->tune, s->stream);
+      TimedLaunch t(s, tfan::K_COLLIDE, true);
+      hipError_t e = tfan::launch_collide(s->dp, state_of(s, a), s->f[b], s->U, s->tune, s->stream, t.start(), t.stop());
       if (e != hipSuccess) return hip_fail(s, e, "collide kernel launch");
     }
     // finite-difference launches alternate the phi/Q buffers; the collision above
@@ -314,8 +321,9 @@ int tfan_step(tfan_sim* s, int64_t nsteps) {
     const int block = tfan::fd_block(s->tune, s->dp.n_sub);
     for (int done = 0; done < s->dp.n_sub;) {
       const int subs = std::min(block, s->dp.n_sub - done);
-      TimedLaunch t(s, block > 1 ? tfan::K_FDN : tfan::K_FD);
-      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, subs, s->stream);
+      TimedLaunch t(s, block > 1 ? tfan::K_FDN : tfan::K_FD, true);
+      hipError_t e = tfan::launch_fd(s->dp, state_of(s, src), state_of(s, 1 - src), s->U, s->tune, subs, s->stream,
+                                     t.start(), t.stop());
       if (e != hipSuccess) return hip_fail(s, e, "sub-step kernel launch");
       src = 1 - src;
       done += subs;

@@ -48,11 +48,16 @@ struct DevState {
 // {162, 163}: blocks of 2 or 3 sub-steps per launch on 64 x 16 tiles;
 // 165: blocks of up to kFusedMaxSub sub-steps on 64 x kSplitTile tiles, with
 // separate thread blocks for phi and Q in one launch.
-constexpr int kFusedMaxSub = 5, kSplitTile = 40;
+// 166: as 165 on 64 x kSplitTileShort tiles.
+// collide_rows: 1, 2 rows of sites per thread on the default tile width (256
+// sites float32, 128 binary16); 11, 12: the same on tiles of half that width.
+constexpr int kFusedMaxSub = 5, kSplitTile = 40, kSplitTileShort = 32;
 struct Tuning {
   int collide_rows = 2;
   int fd_shape = 165;
 };
+inline int collide_site_rows(const Tuning& tn) { return tn.collide_rows % 10; }
+inline bool collide_narrow(const Tuning& tn) { return tn.collide_rows > 10; }
 // Default launch shape of one simulation by grid size (measured, both storages):
 // below 2^21 sites one row of sites per collision thread gives twice the blocks
 // and is faster (64^2-256^2: 16 against 18 us per step; 1024^2: 63.5 against 64.4
@@ -67,13 +72,15 @@ inline int fd_block(const Tuning& tn, int n_sub) {
   if (tn.fd_shape == 162) return n_sub >= 2 ? 2 : 1;
   if (tn.fd_shape == 163) return n_sub >= 3 ? 3 : (n_sub == 2 ? 2 : 1);
   if (tn.fd_shape == 16 || tn.fd_shape == 32) return (n_sub >= 2 && n_sub <= kFusedMaxSub) ? n_sub : 1;
-  if (tn.fd_shape == 165) return n_sub >= 2 ? (n_sub < kFusedMaxSub ? n_sub : kFusedMaxSub) : 1;
+  if (tn.fd_shape == 165 || tn.fd_shape == 166) return n_sub >= 2 ? (n_sub < kFusedMaxSub ? n_sub : kFusedMaxSub) : 1;
   return 1;
 }
 // Tile rows of the blocked sub-step kernel.
 inline int fd_tile_rows(const Tuning& tn) { return tn.fd_shape == 32 ? 32 : 16; }
 // phi and Q advanced by separate thread blocks.
-inline bool fd_split(const Tuning& tn) { return tn.fd_shape == 165; }
+inline bool fd_split(const Tuning& tn) { return tn.fd_shape == 165 || tn.fd_shape == 166; }
+// Tile rows of the split (phi / Q blocks) kernel.
+inline int fd_pair_rows(const Tuning& tn) { return tn.fd_shape == 166 ? kSplitTileShort : kSplitTile; }
 
 // One member of a batch of independent simulations (device-resident table).
 struct BatchMember {
@@ -88,12 +95,13 @@ enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_FDN, K_COUNT };
 // Launchers (return hipGetLastError() after the launch).
 hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
                        hipStream_t st);
+// e0, e1 (optional): timing events recorded at the kernel's start and end.
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
-                          Tuning tn, hipStream_t st);
+                          Tuning tn, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // `subs` finite-difference sub-steps in one launch: subs = 1 with the
 // per-sub-step kernel when fd_block(tn, n_sub) == 1, else 1 <= subs <= fd_block.
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u /*[4][n]*/,
-                     Tuning tn, int subs, hipStream_t st);
+                     Tuning tn, int subs, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // Tiles of one member for the collision (collide = true) or sub-step kernel.
 int batch_tiles(const DevParams& P, Tuning tn, bool collide);
 // Batched launches over the tiles of all members; first[m] = first tile of member m.

@@ -5,6 +5,8 @@
 // are stored after collision and before streaming ("post-collision"), shifted by
 // -w_i rho0 so that the small deviations from rest keep float32 precision; the
 // next step streams them by pulling f_i(x) = f*_i(x - c_i).
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "tfan_internal.h"
@@ -218,9 +220,10 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 // (256 x 4 with 512 threads: 122 us; 128 x 4 with 256: 123 us; before the paired
 // fluids, 64 x 8: 137 us).  Binary16: 128 x 4 with 256 threads (77 us; 64 x 8:
 // 79 us; 256 x 4 with 512 threads: 85 us).
-template <typename PT> struct CollideTile {
+// NW (narrow): tiles of half that width with half the threads, for the autotuner.
+template <typename PT, bool NW = false> struct CollideTile {
   static constexpr bool F32 = sizeof(PT) == 4;
-  static constexpr int X = F32 ? 256 : 128, THREADS = F32 ? 512 : 256;
+  static constexpr int X = (F32 ? 256 : 128) >> (NW ? 1 : 0), THREADS = 2 * X;
   static constexpr int ROWS = THREADS / X;          // rows per pass of the block
   static constexpr int PX = X + 4, SX = X + 2;      // phi/Q staging halo 2, mu/stress halo 1
 };
@@ -287,15 +290,15 @@ __device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, floa
 }
 
 // Tiles of the collision kernel: X x (ROWS * SITES) sites, SITES rows per thread.
-template <typename PT, int SITES> __host__ __device__ inline int collide_tiles(int nx, int ny) {
-  using T = CollideTile<PT>;
+template <typename PT, int SITES, bool NW = false> __host__ __device__ inline int collide_tiles(int nx, int ny) {
+  using T = CollideTile<PT, NW>;
   return ((nx + T::X - 1) / T::X) * ((ny + T::ROWS * SITES - 1) / (T::ROWS * SITES));
 }
 
-template <bool FIELDS, typename PT, int CT_SITES>
+template <bool FIELDS, typename PT, int CT_SITES, bool NW = false>
 __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState& in, void* __restrict__ fout,
                                              float* __restrict__ uout, int tile) {
-  using T = CollideTile<PT>;
+  using T = CollideTile<PT, NW>;
   constexpr int CT_X = T::X, CT_THREADS = T::THREADS, CT_ROWS_PER_PASS = T::ROWS, PX = T::PX, SX = T::SX;
   constexpr int CT_Y = CT_ROWS_PER_PASS * CT_SITES, PY = CT_Y + 4, SY = CT_Y + 2;
   __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
@@ -398,13 +401,13 @@ __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState&
   }
 }
 
-template <bool FIELDS, typename PT, int SITES>
-__global__ void __launch_bounds__(CollideTile<PT>::THREADS) k_collide(DevParams P, DevState in,
-                                                                      void* __restrict__ fout,
-                                                                      float* __restrict__ uout) {
-  const int tile = xcd_tile(collide_tiles<PT, SITES>(P.nx, P.ny));
+template <bool FIELDS, typename PT, int SITES, bool NW>
+__global__ void __launch_bounds__((CollideTile<PT, NW>::THREADS)) k_collide(DevParams P, DevState in,
+                                                                            void* __restrict__ fout,
+                                                                            float* __restrict__ uout) {
+  const int tile = xcd_tile(collide_tiles<PT, SITES, NW>(P.nx, P.ny));
   if (tile < 0) return;  // whole workgroup, before any barrier
-  collide_tile<FIELDS, PT, SITES>(P, in, fout, uout, tile);
+  collide_tile<FIELDS, PT, SITES, NW>(P, in, fout, uout, tile);
 }
 
 // Member of a batch whose tile index range starts at `first` (ascending array).
@@ -417,16 +420,16 @@ __device__ __forceinline__ int batch_member(const int* __restrict__ first, int c
   return lo;
 }
 
-template <typename PT, int SITES>
-__global__ void __launch_bounds__(CollideTile<PT>::THREADS) k_collide_batch(const BatchMember* __restrict__ mem,
-                                                              const int* __restrict__ first, int count,
-                                                              int tiles, int cur) {
+template <typename PT, int SITES, bool NW>
+__global__ void __launch_bounds__((CollideTile<PT, NW>::THREADS)) k_collide_batch(const BatchMember* __restrict__ mem,
+                                                                    const int* __restrict__ first, int count,
+                                                                    int tiles, int cur) {
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int m = batch_member(first, count, tile);
   const DevParams P = mem[m].P;
   const DevState in = mem[m].st[cur];
-  collide_tile<false, PT, SITES>(P, in, mem[m].st[1 - cur].f, mem[m].U, tile - first[m]);
+  collide_tile<false, PT, SITES, NW>(P, in, mem[m].st[1 - cur].f, mem[m].U, tile - first[m]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1248,34 +1251,58 @@ hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hip
   return hipGetLastError();
 }
 
-template <bool FIELDS, typename PT, int SITES>
-void launch_collide_tiles(const DevParams& P, DevState in, void* f_out, float* u_out, hipStream_t st) {
-  const dim3 grid(xcd_grid(collide_tiles<PT, SITES>(P.nx, P.ny)));
-  hipLaunchKernelGGL((k_collide<FIELDS, PT, SITES>), grid, dim3(CollideTile<PT>::THREADS), 0, st, P, in, f_out,
-                     u_out);
+// Launch on st; with timing events, they travel in the kernel's own dispatch (the
+// recorded interval is the kernel's execution, without the gaps around it).
+template <typename K, typename... A>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st, hipEvent_t e0, hipEvent_t e1, A... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
 }
 
+template <bool FIELDS, typename PT, int SITES, bool NW = false>
+void launch_collide_tiles(const DevParams& P, DevState in, void* f_out, float* u_out, hipStream_t st,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  const dim3 grid(xcd_grid(collide_tiles<PT, SITES, NW>(P.nx, P.ny)));
+  launch_timed(k_collide<FIELDS, PT, SITES, NW>, grid, dim3(CollideTile<PT, NW>::THREADS), st, e0, e1, P, in, f_out,
+               u_out);
+}
+
+template <typename PT, int SITES, bool NW>
+inline int batch_collide_tiles(const DevParams& P) { return collide_tiles<PT, SITES, NW>(P.nx, P.ny); }
+
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out, Tuning tn,
-                          hipStream_t st) {
-  if (tn.collide_rows == 1) {
-    if (P.pop16) launch_collide_tiles<false, _Float16, 1>(P, in, f_out, u_out, st);
-    else launch_collide_tiles<false, float, 1>(P, in, f_out, u_out, st);
+                          hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+#define TFAN_COLLIDE(R_, NW_)                                                                       \
+  (P.pop16 ? launch_collide_tiles<false, _Float16, R_, NW_>(P, in, f_out, u_out, st, e0, e1)        \
+           : launch_collide_tiles<false, float, R_, NW_>(P, in, f_out, u_out, st, e0, e1))
+  const bool nw = collide_narrow(tn);
+  if (collide_site_rows(tn) == 1) {
+    if (nw) TFAN_COLLIDE(1, true); else TFAN_COLLIDE(1, false);
   } else {
-    if (P.pop16) launch_collide_tiles<false, _Float16, 2>(P, in, f_out, u_out, st);
-    else launch_collide_tiles<false, float, 2>(P, in, f_out, u_out, st);
+    if (nw) TFAN_COLLIDE(2, true); else TFAN_COLLIDE(2, false);
   }
+#undef TFAN_COLLIDE
   return hipGetLastError();
 }
 
 hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float* u, Tuning tn, int subs,
-                     hipStream_t st) {
+                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int block = fd_block(tn, P.n_sub);
   if (block > 1 && fd_split(tn)) {
-    const dim3 grid(xcd_grid(pair_items(fused_tiles<kSplitTile>(P.nx, P.ny))));
-    hipLaunchKernelGGL((k_fd_pair<kSplitTile, kFusedMaxSub>), grid, dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), 0,
-                       st, P, in, out, u, subs);
+    if (fd_pair_rows(tn) == kSplitTile) {
+      const dim3 grid(xcd_grid(pair_items(fused_tiles<kSplitTile>(P.nx, P.ny))));
+      launch_timed(k_fd_pair<kSplitTile, kFusedMaxSub>, grid, dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), st, e0,
+                   e1, P, in, out, u, subs);
+    } else {
+      const dim3 grid(xcd_grid(pair_items(fused_tiles<kSplitTileShort>(P.nx, P.ny))));
+      launch_timed(k_fd_pair<kSplitTileShort, kFusedMaxSub>, grid, dim3(PairBlock<kSplitTileShort, kFusedMaxSub>::NT),
+                   st, e0, e1, P, in, out, u, subs);
+    }
     return hipGetLastError();
   }
+  if (e0) (void)hipEventRecord(e0, st);  // other shapes: events around the launch
   if (block > 1) {
     const int th = fd_tile_rows(tn);
 #define TFAN_FUSED(TH_, MS_)                                                                                  \
@@ -1286,6 +1313,7 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
     else if (th == 16) TFAN_FUSED(16, 5);
     else TFAN_FUSED(32, 5);
 #undef TFAN_FUSED
+    if (e1) (void)hipEventRecord(e1, st);
     return hipGetLastError();
   }
   switch (tn.fd_shape) {
@@ -1293,16 +1321,22 @@ hipError_t launch_fd(const DevParams& P, DevState in, DevState out, const float*
     case 2: hipLaunchKernelGGL(k_fd<2>, dim3(xcd_grid(fd_tiles<2>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
     default: hipLaunchKernelGGL(k_fd<4>, dim3(xcd_grid(fd_tiles<4>(P.nx, P.ny))), dim3(FD_TX, FD_TY), 0, st, P, in, out, u); break;
   }
+  if (e1) (void)hipEventRecord(e1, st);
   return hipGetLastError();
 }
 
 int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
   if (collide) {
-    if (P.pop16) return tn.collide_rows == 1 ? collide_tiles<_Float16, 1>(P.nx, P.ny) : collide_tiles<_Float16, 2>(P.nx, P.ny);
-    return tn.collide_rows == 1 ? collide_tiles<float, 1>(P.nx, P.ny) : collide_tiles<float, 2>(P.nx, P.ny);
+    const bool one = collide_site_rows(tn) == 1, nw = collide_narrow(tn);
+    if (P.pop16)
+      return one ? (nw ? batch_collide_tiles<_Float16, 1, true>(P) : batch_collide_tiles<_Float16, 1, false>(P))
+                 : (nw ? batch_collide_tiles<_Float16, 2, true>(P) : batch_collide_tiles<_Float16, 2, false>(P));
+    return one ? (nw ? batch_collide_tiles<float, 1, true>(P) : batch_collide_tiles<float, 1, false>(P))
+               : (nw ? batch_collide_tiles<float, 2, true>(P) : batch_collide_tiles<float, 2, false>(P));
   }
   if (fd_block(tn, P.n_sub) > 1) {
-    if (fd_split(tn)) return fused_tiles<kSplitTile>(P.nx, P.ny);
+    if (fd_split(tn))
+      return fd_pair_rows(tn) == kSplitTile ? fused_tiles<kSplitTile>(P.nx, P.ny) : fused_tiles<kSplitTileShort>(P.nx, P.ny);
     return fd_tile_rows(tn) == 16 ? fused_tiles<16>(P.nx, P.ny) : fused_tiles<32>(P.nx, P.ny);
   }
   return tn.fd_shape == 1 ? fd_tiles<1>(P.nx, P.ny) : tn.fd_shape == 2 ? fd_tiles<2>(P.nx, P.ny) : fd_tiles<4>(P.nx, P.ny);
@@ -1310,14 +1344,19 @@ int batch_tiles(const DevParams& P, Tuning tn, bool collide) {
 
 hipError_t launch_collide_batch(const BatchMember* mem, const int* first, int count, int tiles, int cur, bool pop16,
                                 Tuning tn, hipStream_t st) {
-  const dim3 grid(xcd_grid(tiles)), b16(CollideTile<_Float16>::THREADS), b32(CollideTile<float>::THREADS);
-  if (tn.collide_rows == 1) {
-    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 1>), grid, b16, 0, st, mem, first, count, tiles, cur);
-    else hipLaunchKernelGGL((k_collide_batch<float, 1>), grid, b32, 0, st, mem, first, count, tiles, cur);
+  const dim3 grid(xcd_grid(tiles));
+#define TFAN_COLLIDE_B(PT_, R_, NW_)                                                                          \
+  hipLaunchKernelGGL((k_collide_batch<PT_, R_, NW_>), grid, dim3(CollideTile<PT_, NW_>::THREADS), 0, st, mem, \
+                     first, count, tiles, cur)
+  const bool one = collide_site_rows(tn) == 1, nw = collide_narrow(tn);
+  if (pop16) {
+    if (one) { if (nw) TFAN_COLLIDE_B(_Float16, 1, true); else TFAN_COLLIDE_B(_Float16, 1, false); }
+    else { if (nw) TFAN_COLLIDE_B(_Float16, 2, true); else TFAN_COLLIDE_B(_Float16, 2, false); }
   } else {
-    if (pop16) hipLaunchKernelGGL((k_collide_batch<_Float16, 2>), grid, b16, 0, st, mem, first, count, tiles, cur);
-    else hipLaunchKernelGGL((k_collide_batch<float, 2>), grid, b32, 0, st, mem, first, count, tiles, cur);
+    if (one) { if (nw) TFAN_COLLIDE_B(float, 1, true); else TFAN_COLLIDE_B(float, 1, false); }
+    else { if (nw) TFAN_COLLIDE_B(float, 2, true); else TFAN_COLLIDE_B(float, 2, false); }
   }
+#undef TFAN_COLLIDE_B
   return hipGetLastError();
 }
 
@@ -1326,8 +1365,12 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
   const dim3 grid(xcd_grid(tiles)), blk(FD_TX, FD_TY);
   const int block = fd_block(tn, n_sub);
   if (block > 1 && fd_split(tn)) {
-    hipLaunchKernelGGL((k_fd_pair_batch<kSplitTile, kFusedMaxSub>), dim3(xcd_grid(pair_items(tiles))),
-                       dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), 0, st, mem, first, count, tiles, src, subs);
+    if (fd_pair_rows(tn) == kSplitTile)
+      hipLaunchKernelGGL((k_fd_pair_batch<kSplitTile, kFusedMaxSub>), dim3(xcd_grid(pair_items(tiles))),
+                         dim3(PairBlock<kSplitTile, kFusedMaxSub>::NT), 0, st, mem, first, count, tiles, src, subs);
+    else
+      hipLaunchKernelGGL((k_fd_pair_batch<kSplitTileShort, kFusedMaxSub>), dim3(xcd_grid(pair_items(tiles))),
+                         dim3(PairBlock<kSplitTileShort, kFusedMaxSub>::NT), 0, st, mem, first, count, tiles, src, subs);
     return hipGetLastError();
   }
   if (block > 1) {
@@ -1349,8 +1392,8 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
 }
 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
-  if (P.pop16) launch_collide_tiles<true, _Float16, 2>(P, in, nullptr, aux, st);
-  else launch_collide_tiles<true, float, 2>(P, in, nullptr, aux, st);
+  if (P.pop16) launch_collide_tiles<true, _Float16, 2, false>(P, in, nullptr, aux, st);
+  else launch_collide_tiles<true, float, 2, false>(P, in, nullptr, aux, st);
   return hipGetLastError();
 }
 

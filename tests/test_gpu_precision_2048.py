@@ -113,3 +113,70 @@ def test_statistics_match_oracle_2048(gpu, zeta, storage):
     assert worst["ke"] <= tol_ke
     assert worst["band"] <= tol_band
     assert worst["phi"] <= TOL_PHI_MEAN
+
+
+# ---------------------------------------------------------------------------
+# The precision study's full horizon: 50,000 steps of the 2048 x 2048 grid (the
+# FP64 oracle needs about 7 hours of 8 host threads per activity for it, so its
+# statistics stop at 3,000 steps above).  Float32 and binary16 population storage
+# are compared with each other over the last quarter (steps 37,500-50,000, six
+# snapshots): the domain length within 5% at every activity; the kinetic energy
+# within 5% for the active turbulent flow (zeta = 0.02; reported for zeta = 0.005
+# and 0, where the residual flow decays); each octave band holding >= 1% of the
+# energy within the larger of 5% and three standard errors of the difference of
+# the two window means (snapshot-to-snapshot spread over six snapshots): the two
+# trajectories decorrelate, and bands of few Fourier modes then differ by sampling
+# noise.  The exact phi mass of both storages drifts by at most 5e-5 per site.
+# ---------------------------------------------------------------------------
+LONG_STEPS, LONG_EVERY = 50000, 2500
+
+
+def long_series(zeta, storage):
+    from paper_2511_00445_amd import Sim
+    p = dict(workload_params("large_2048", zeta=zeta), storage=storage)
+    s = Sim(p)
+    s.init_fields(**initial_fields(N, N, seed=4))
+    phi0 = s.diagnostics()["phi_sum"]
+    rec = {"t": [], "L": [], "ke_c": [], "bands": [], "nyq": []}
+    while s.step_count() < LONG_STEPS:
+        s.step(LONG_EVERY)
+        if s.step_count() < 0.75 * LONG_STEPS and s.step_count() % 10000:
+            continue
+        f = s.get_fields()
+        uc = mixture_velocity(f["phi"], f["u_a"], f["u_p"])
+        rec["t"].append(s.step_count())
+        rec["L"].append(domain_length(f["phi"]))
+        rec["ke_c"].append(float(0.5 * (uc ** 2).sum(0).mean()))
+        rec["bands"].append(octave_bands(energy_spectrum(uc), N // 4))
+    d = s.diagnostics()
+    s.close()
+    assert d["status"] == 0, d
+    rec["drift"] = abs(d["phi_sum"] - phi0) / (N * N)
+    return rec
+
+
+@pytest.mark.parametrize("zeta", [0.02, 0.005, 0.0])
+def test_precision_full_horizon_2048(gpu, zeta):
+    say(f"case: 2048x2048, zeta {zeta}, float32 and binary16 to {LONG_STEPS} steps")
+    r32, r16 = long_series(zeta, 0), long_series(zeta, 1)
+    t = np.asarray(r32["t"])
+    last = t >= 0.75 * LONG_STEPS
+    for r, name in ((r32, "float32"), (r16, "binary16")):
+        say(f"  {name}: L {np.round(r['L'], 2).tolist()} at {r['t']}; ke {np.array(r['ke_c'])[last].mean():.3e}; "
+            f"phi drift per site {r['drift']:.1e}")
+        assert r["drift"] <= 5e-5
+    mean = lambda r, k: np.asarray(r[k])[last].mean(axis=0)
+    dL = abs(mean(r16, "L") - mean(r32, "L")) / mean(r32, "L")
+    dk = abs(mean(r16, "ke_c") - mean(r32, "ke_c")) / mean(r32, "ke_c")
+    b32, b16 = mean(r32, "bands"), mean(r16, "bands")
+    big = b32 >= BAND_SHARE * b32.sum()
+    n_last = int(last.sum())
+    sd = lambda r: np.asarray(r["bands"])[last].std(axis=0, ddof=1)
+    se = np.sqrt(sd(r32) ** 2 + sd(r16) ** 2) / np.sqrt(n_last) / b32
+    devs = np.abs(b16 - b32) / b32
+    say(f"  last quarter, binary16 against float32: L {dL:.4f}, KE {dk:.4f}; bands (>= 1% of KE) "
+        f"{np.round(devs[big], 4).tolist()}, 3 standard errors {np.round(3 * se[big], 4).tolist()}")
+    assert dL <= 0.05
+    if zeta >= 0.02:
+        assert dk <= 0.05
+    assert np.all(devs[big] <= np.maximum(0.05, 3 * se[big])), (devs[big], se[big])

@@ -6,17 +6,17 @@ statistics are compared: the domain length L(t), the mixture kinetic energy and
 octave-band sums of E(k) up to N/4.  The oracle's seed-to-seed spread (seeds 1-3)
 is printed beside every deviation as the noise floor of the statistic.
 
-Windows.  From about step 12,000 a grid-scale (checkerboard) velocity mode, which
-the collocated central differences of the scheme leave undamped in the mixture,
-grows in both implementations; by the last quarter (15,000-20,000) it carries
-a large share of the kinetic energy, its growth phase depends on rounding, and
-the oracle's own seed spread is 20-60% in KE and in the low bands.  Hence:
-  - L(t) at log-spaced times up to 16,000: within 5% (both storages);
-  - steps 9,000-12,000 (the last quarter of the run before the mode holds 1e-3 of
-    the velocity variance): mean L, mean KE and every band within 5% (both);
-  - last quarter: mean L within 5% (both); float32 also KE and the bands n >= 2
-    within 5%; the single-shell band n = 1 and the binary16 KE and bands are
-    reported with the seed spread.
+Asserted:
+  - L(t) at log-spaced times 500 ... 16,000: within 5% (both storages);
+  - the last quarter of the run (steps 15,000-20,000): mean L and mean kinetic
+    energy within 5% (both storages); every octave band within 5% for float32
+    (the plain path); for binary16 storage each band within the larger of 5% and
+    the oracle's own seed-to-seed spread of that band.  Binary16 trajectories
+    leave the FP64 one within the run, and the two lowest bands hold 8 and 31
+    Fourier modes, whose energies then differ by sampling noise (oracle seed
+    spread 70% and 19%) rather than by precision;
+  - no grid-scale velocity mode: the share of the variance of u_a in the rows
+    and columns within 2 of the Nyquist index stays below 1e-4 in both.
 """
 import sys
 
@@ -28,7 +28,8 @@ from tests.longstats import at_times, gpu_record, load_golden, rel_dev, window_s
 pytestmark = pytest.mark.gpu
 TOL = 0.05
 LOG_TIMES = (500, 1000, 2000, 4000, 8000, 16000)
-WINDOWS = {"last_quarter": (15000, 20000), "pre_onset": (9000, 12000)}
+LAST_QUARTER = (15000, 20000)
+GRID_SCALE_MAX = 1e-4
 
 
 def say(msg):
@@ -65,26 +66,21 @@ def test_long_time_statistics(gpu, seed, storage):
         f"oracle {np.round(at_times(ref, LOG_TIMES), 3).tolist()} rel dev {np.round(dL, 4).tolist()}")
     assert np.all(dL <= TOL), dL
 
-    for name, (t0, t1) in WINDOWS.items():
-        g, o = window_stats(rec, t0, t1), window_stats(ref, t0, t1)
-        spread = seed_spread(golden, t0, t1)
-        dl = float(rel_dev(g["L"], o["L"]))
-        dk = float(rel_dev(g["ke_c"], o["ke_c"]))
-        db = rel_dev(g["bands"], o["bands"])
-        say(f"{name} [{t0},{t1}]: L dev {dl:.4f} (seed spread {spread['L']:.4f}); "
-            f"KE dev {dk:.4f} (spread {spread['ke_c']:.4f}); band devs "
-            f"{np.round(db, 4).tolist()} (spread {np.round(spread['bands'], 4).tolist()})")
-        assert dl <= TOL, (name, dl)
-        if name == "pre_onset":
-            assert dk <= TOL and np.all(db <= TOL), (name, dk, db)
-        elif storage == 0:
-            assert dk <= TOL and np.all(db[1:] <= TOL), (name, dk, db)
+    t0, t1 = LAST_QUARTER
+    g, o = window_stats(rec, t0, t1), window_stats(ref, t0, t1)
+    spread = seed_spread(golden, t0, t1)
+    dl = float(rel_dev(g["L"], o["L"]))
+    dk = float(rel_dev(g["ke_c"], o["ke_c"]))
+    db = rel_dev(g["bands"], o["bands"])
+    say(f"last quarter [{t0},{t1}]: L dev {dl:.4f} (seed spread {spread['L']:.4f}); "
+        f"KE dev {dk:.4f} (spread {spread['ke_c']:.4f}); band devs "
+        f"{np.round(db, 4).tolist()} (spread {np.round(spread['bands'], 4).tolist()})")
+    assert dl <= TOL and dk <= TOL, (dl, dk)
+    if storage == 0:
+        assert np.all(db <= TOL), db
+    else:
+        assert np.all(db <= np.maximum(TOL, spread["bands"])), (db, spread["bands"])
 
-    # the grid-scale mode: negligible before the pre-onset window ends in both, and
-    # where the oracle's share exceeds 10% the GPU run shows it too
-    t = np.asarray(ref["t"])
-    pre = t <= WINDOWS["pre_onset"][1]
-    assert max(np.asarray(ref["nyq"])[pre]) < 1e-3 and max(np.asarray(rec["nyq"])[pre]) < 1e-3
-    late = np.asarray(ref["nyq"]) > 0.1
-    if late.any():
-        assert np.all(np.asarray(rec["nyq"])[late] > 0.02), (np.asarray(rec["nyq"])[late])
+    nyq_o, nyq_g = max(ref["nyq"]), max(rec["nyq"])
+    say(f"largest grid-scale share of u_a: oracle {nyq_o:.2e}, gpu {nyq_g:.2e}")
+    assert nyq_o < GRID_SCALE_MAX and nyq_g < GRID_SCALE_MAX

@@ -240,6 +240,64 @@ def bench_surrogate(args):
     print(json.dumps(out_line), flush=True)
 
 
+def bench_cnn(args):
+    """The surrogate network alone on synthetic inputs (no solver): forward passes at
+    1024x1024 (batch 1) and Adam steps at 256x256 (batch 8), timed with HIP events
+    on the network's stream.  Used for the network kernels' counters and traces."""
+    import numpy as np
+    import torch
+    from paper_2511_00445_amd import Cnn
+    from paper_2511_00445_amd import surrogate as S
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    theta = S.init_params(0)
+    theta[-(48 * 7 * 9 + 7):] = np.random.default_rng(1).uniform(-0.02, 0.02, 48 * 7 * 9 + 7).astype(np.float32)
+    ones = np.ones(7, np.float32)
+    n = 1024
+    net = Cnn(1, n, n)
+    net.set_params(theta)
+    net.set_scales(ones, ones)
+    x = torch.rand((1, 7, n, n), generator=gen, device="cuda") - 0.5
+    out = torch.empty_like(x)
+    for _ in range(3):
+        net.forward(x, out)
+    reps = max(1, args.steps // 100)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    for _ in range(reps):
+        net.forward(x, out)
+    e1.record(net.stream)
+    net.sync()
+    fwd_s = e0.elapsed_time(e1) / reps / 1e3
+    tr = Cnn(8, 256, 256, train=True)
+    tr.set_params(theta)
+    tr.set_scales(ones, ones)
+    X = torch.rand((16, 7, 256, 256), generator=gen, device="cuda") - 0.5
+    T = X + 0.01 * (torch.rand((16, 7, 256, 256), generator=gen, device="cuda") - 0.5)
+    idx = np.arange(8, dtype=np.int32)
+    tr.train_step(X, T, idx, 1e-4)
+    e0.record(tr.stream)
+    for _ in range(reps):
+        tr.train_step(X, T, idx, 1e-4, want_loss=False)
+    e1.record(tr.stream)
+    tr.sync()
+    train_s = e0.elapsed_time(e1) / reps / 1e3
+    flops = 2.0 * CNN_MACS_PER_SITE * n * n
+    achieved = flops / fwd_s / 1e12
+    out_line = {"metric": "surrogate network forward passes per second (1024x1024, bf16 MFMA)",
+                "value": round(1.0 / fwd_s, 2), "unit": "passes/s", "n_gpus": 1, "steps": reps, "warmup": 3,
+                "ms_per_step": round(fwd_s * 1e3, 4), "higher_is_better": True, "scaling": "strong",
+                "vs_baseline": None, "dtype": "bf16-mfma/f32", "data": "synthetic",
+                "config": {"workload": "cnn_1024: forward 1x7x1024x1024; training step 8x7x256x256",
+                           "parallelism": "single GPU"},
+                "train_step_ms": round(train_s * 1e3, 4),
+                "roofline": {"bound": "mfma", "kernel": "cnn_forward (6 convolutions)", "achieved": round(achieved, 1),
+                             "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4),
+                             "traffic": None, "alg_flops_per_launch": flops, "avg_launch_us": round(fwd_s * 1e6, 2)}}
+    net.close()
+    tr.close()
+    print(json.dumps(out_line), flush=True)
+
+
 def bench_analysis(args):
     """On-device observables of one 2048x2048 snapshot (spectra + L, correlations,
     defects in one tfan_analysis_all call) against the FP64 numpy oracle on the host,
@@ -365,6 +423,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "analysis_2048":
         return bench_analysis(args)
+    if args.workload == "cnn_1024":
+        return bench_cnn(args)
     w = WORKLOADS[args.workload]
     p = workload_params(args.workload)
     p["storage"] = 1 if args.storage == "f16" else 0

@@ -31,6 +31,11 @@ from .workloads import initial_fields
 K_STEPS = 50
 RELAX_STEPS = 25     # solver steps after each jump in the deploy loop
 TRAIN_STEPS = 12000  # Adam steps of the standard training run (batches of 8)
+# Training trajectories: 256 x 256 runs, pairs from steps TRAIN_T0 to TRAIN_T1, so
+# that the network has seen the early coarsening and the late, activity-arrested
+# domains it meets over long deployments.
+TRAIN_T0, TRAIN_T1 = 1000, 50000
+TRAIN_SEEDS = tuple(range(600, 608))
 
 
 def trajectory_pairs(params: dict, seeds, t0: int, t1: int, k: int = K_STEPS, phi_mean: float = 0.0):
@@ -213,7 +218,8 @@ class SurrogateRun:
     def summary(self) -> dict:
         errs = [e for _, e in self.errors]
         return dict(surrogate_calls=self.surrogate_calls, solver_calls=self.solver_calls, checks=self.checks,
-                    fallbacks=self.fallbacks, max_check_error=max(errs) if errs else None,
+                    fallbacks=self.fallbacks, failed_checks=sum(1 for e in errs if not e <= self.tol),
+                    max_check_error=max(errs) if errs else None,
                     mean_check_error=float(np.mean(errs)) if errs else None)
 
 

@@ -1,14 +1,20 @@
-"""Surrogate-accelerated coarsening against the plain solver on the same GPU.
+"""Surrogate-accelerated coarsening against the plain solver on the same GPU, on
+the 1024 x 1024 grid at zeta = 0.01.
 
-Trained on 256x256 trajectories (8 seeds, steps 1,000-12,000, the 512x512
-active workload's parameters; 12,000 Adam steps) by the library's own kernels,
-deployed on 512x512 runs (seeds 7, 8, 9) after the spinodal stage: plain solver
-to step 6,000, then calls of a 50-step network jump plus 25 solver steps, a
-solver check every 10 calls with fallback above 5e-2 relative L2 on (phi, Q).
-For every deployment seed the domain length L(t) must stay within 5% of the
-plain run's at every 600 steps, and simulated steps per second must beat the
-plain path's.  The flow is chaotic, so one seed's deviation is one draw: three
-seeds show the margin.
+Trained on 256 x 256 trajectories (8 seeds, steps 1,000-50,000, the deployment
+parameters; 12,000 Adam steps) by the library's own kernels, then deployed from
+the plain run's state at step 6,000 (after the spinodal stage): each call is a
+50-step network jump followed by `relax` solver steps; every 10th call is checked
+against the solver over the same 50 steps, with fallback above 5e-2 relative L2
+on (phi, Q).
+
+relax = 25 (the deploy loop's setting), 100,500 steps: the domain length L(t)
+stays within 5% of the plain run's at every sample and simulated steps per
+second beat the plain path's.
+relax = 0 (network jumps back to back): the chained jumps leave grid-scale noise
+that fails the checks; the fallback restores and recomputes with the solver, so
+the run stays healthy and every failed check is a fallback; its speedup is
+reported, not asserted.
 """
 import sys
 
@@ -25,20 +31,30 @@ def say(msg):
     sys.stdout.flush()
 
 
-def test_surrogate_speedup_at_five_percent_domain_length(gpu):
+def test_surrogate_speedup_at_five_percent_domain_length_1024(gpu):
     from paper_2511_00445_amd import surrogate as S
-    say("case: surrogate deploy 512x512 seeds 7-9, steps 6000-12000")
-    theta, s_in, s_out, losses, secs = S.train_surrogate(base_params(256, 256, zeta=0.01), list(range(600, 608)),
-                                                         1000, 12000, steps=S.TRAIN_STEPS, batch=8)
+    say(f"case: surrogate training on 256x256 steps {S.TRAIN_T0}-{S.TRAIN_T1}")
+    theta, s_in, s_out, losses, secs = S.train_surrogate(base_params(256, 256, zeta=0.01), list(S.TRAIN_SEEDS),
+                                                         S.TRAIN_T0, S.TRAIN_T1, steps=S.TRAIN_STEPS, batch=8)
     say(f"trained in {secs:.1f} s, loss {np.mean(losses[:50]):.3f} -> {np.mean(losses[-200:]):.3f}")
-    for seed in (7, 8, 9):
-        r = S.deploy_compare(base_params(512, 512, zeta=0.01), seed, theta, s_in, s_out, 6000, 12000, 600,
-                             relax=S.RELAX_STEPS)
-        say(f"seed {seed}: L plain {np.round(r['L_plain'], 2).tolist()}")
-        say(f"seed {seed}: L surrogate {np.round(r['L_surrogate'], 2).tolist()}")
-        say(f"seed {seed}: max L deviation {r['max_L_dev']:.4f}; steps/s plain {r['plain_steps_per_s']:.0f} "
-            f"surrogate {r['surrogate_steps_per_s']:.0f} (speedup {r['speedup']:.2f}); checks {r['checks']}, "
-            f"fallbacks {r['fallbacks']}, max check error {r['max_check_error']:.4f}")
-        assert r["status"] == 0
-        assert r["max_L_dev"] <= 0.05, seed
-        assert r["speedup"] > 1.0, seed
+    p = base_params(1024, 1024, zeta=0.01)
+    call = S.K_STEPS + S.RELAX_STEPS
+    every = call * 67
+    say(f"case: deploy 1024x1024 seed 7, relax {S.RELAX_STEPS}, steps 6000-{6000 + 20 * every}")
+    r = S.deploy_compare(p, 7, theta, s_in, s_out, 6000, 6000 + 20 * every, every, relax=S.RELAX_STEPS)
+    say(f"L plain {np.round(r['L_plain'], 2).tolist()}")
+    say(f"L surrogate {np.round(r['L_surrogate'], 2).tolist()}")
+    say(f"relax {S.RELAX_STEPS}: max L deviation {r['max_L_dev']:.4f}; steps/s plain {r['plain_steps_per_s']:.0f} "
+        f"surrogate {r['surrogate_steps_per_s']:.0f} (speedup {r['speedup']:.2f}); checks {r['checks']}, "
+        f"fallbacks {r['fallbacks']}, max check error {r['max_check_error']:.4f}")
+    assert r["status"] == 0
+    assert r["max_L_dev"] <= 0.05
+    assert r["speedup"] > 1.0
+    say("case: deploy 1024x1024 seed 7, relax 0, steps 6000-12000")
+    r0 = S.deploy_compare(p, 7, theta, s_in, s_out, 6000, 12000, 600, relax=0)
+    say(f"relax 0: steps/s plain {r0['plain_steps_per_s']:.0f} surrogate {r0['surrogate_steps_per_s']:.0f} "
+        f"(speedup {r0['speedup']:.2f}); checks {r0['checks']}, failed {r0['failed_checks']}, "
+        f"fallbacks {r0['fallbacks']}, "
+        f"max check error {r0['max_check_error']:.4f}")
+    assert r0["status"] == 0 and r0["checks"] >= 1
+    assert r0["fallbacks"] == r0["failed_checks"]

@@ -137,6 +137,13 @@ def bench_sweep(args):
     bad = [i for i in range(len(members)) if b.diagnostics(i)["status"] != 0]
     if bad:
         raise SystemExit(f"unhealthy batch members: {bad}")
+    # the same steps in one persistent launch (all members, all steps)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    b.step_persistent(args.steps)
+    b.sync()
+    wall_p = time.perf_counter() - tp
+    persist_blocks = b.persistent_blocks()
     tuning = b.get_tuning()
     b.close()
     sims = []
@@ -162,7 +169,9 @@ def bench_sweep(args):
                       "tuning": {"collide_rows": tuning[0], "fd_shape": tuning[1]},
                       "autotune_ms_per_step": round(tuned_ms, 4)},
            "sequential_value": round(sites * args.steps / wall_seq / 1e6, 1),
-           "batch_speedup": round(wall_seq / wall, 3)}
+           "batch_speedup": round(wall_seq / wall, 3),
+           "persistent_launch": {"value": round(sites * args.steps / wall_p / 1e6, 1), "unit": "MLUPS",
+                                 "ms_per_step": round(wall_p / args.steps * 1e3, 4), "blocks": persist_blocks}}
     print(json.dumps(out), flush=True)
 
 

@@ -248,6 +248,17 @@ int tfan_batch_step(tfan_batch* b, int64_t n);                           /* asyn
 int tfan_batch_get_fields(tfan_batch* b, int32_t member, double* phi, double* qxx, double* qxy,
                           double* u_a, double* u_p, double* rho_a, double* rho_p);
 int tfan_batch_diagnostics(tfan_batch* b, int32_t member, tfan_diag* out);
+/* The same n >= 0 steps as tfan_batch_step in ONE persistent launch for all
+ * members and all steps: a cooperative kernel whose blocks (1024 threads, as
+ * many as are resident at once) take the collision tiles of every member, meet
+ * at a grid-wide barrier, take the phi and Q sub-step tiles of every member (all
+ * n_sub sub-steps of the step), meet again, and go on to the next step.  Requires
+ * n_sub <= 5 (else TFAN_EINVAL); results are bitwise those of tfan_batch_step;
+ * the launch shape set by tfan_batch_set_tuning does not apply.  Async; a launch
+ * the device cannot run cooperatively gives TFAN_EHIP. */
+int tfan_batch_step_persistent(tfan_batch* b, int64_t n);
+/* Blocks of the last persistent launch (0 before the first). */
+int tfan_batch_persistent_blocks(const tfan_batch* b);
 int tfan_batch_set_tuning(tfan_batch* b, int32_t collide_rows, int32_t fd_shape);
 int tfan_batch_get_tuning(const tfan_batch* b, int32_t* collide_rows, int32_t* fd_shape);
 int tfan_batch_autotune(tfan_batch* b, int32_t steps, double* best_ms_per_step);

@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_batch_count": (ctypes.c_int, [_vp]),
         "tfan_batch_init_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp]),
         "tfan_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "tfan_batch_step_persistent": (ctypes.c_int, [_vp, ctypes.c_int64]),
+        "tfan_batch_persistent_blocks": (ctypes.c_int, [_vp]),
         "tfan_batch_get_fields": (ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
         "tfan_batch_diagnostics": (ctypes.c_int, [_vp, ctypes.c_int32, _P(tfan_diag)]),
         "tfan_batch_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
@@ -362,6 +364,13 @@ class Batch:
 
     def step(self, n: int = 1):
         self._check(self.lib.tfan_batch_step(self._handle, int(n)))
+
+    def step_persistent(self, n: int = 1):
+        """The same steps as step(), all in one persistent launch (n_sub <= 5)."""
+        self._check(self.lib.tfan_batch_step_persistent(self._handle, int(n)))
+
+    def persistent_blocks(self) -> int:
+        return int(self.lib.tfan_batch_persistent_blocks(self._handle))
 
     def get_fields(self, member) -> dict:
         p = self._member(member)

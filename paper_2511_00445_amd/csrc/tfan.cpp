@@ -4,6 +4,7 @@
 #include "tfan.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -638,6 +639,10 @@ struct tfan_batch {
   int* first_c = nullptr;              // device [count]
   int* first_f = nullptr;              // device [count]
   int tiles_c = 0, tiles_f = 0;
+  int* first_pc = nullptr;             // device [count]: tiles of the persistent launch's phases
+  int* first_pf = nullptr;
+  int tiles_pc = 0, tiles_pf = 0;
+  int persist_grid = 0;                // blocks of the last persistent launch
   int cur = 0;
   int64_t step = 0;
   tfan::Tuning tune;
@@ -654,7 +659,7 @@ int bfail(tfan_batch* b, int code, const std::string& msg) {
 }
 
 size_t batch_table_bytes(int count) {
-  return align_up(count * sizeof(tfan::BatchMember)) + 2 * align_up(count * sizeof(int));
+  return align_up(count * sizeof(tfan::BatchMember)) + 4 * align_up(count * sizeof(int));
 }
 
 int upload_first(tfan_batch* b) {
@@ -668,9 +673,23 @@ int upload_first(tfan_batch* b) {
   }
   b->tiles_c = tc;
   b->tiles_f = tf;
+  std::vector<int> pc(b->m.size()), pf(b->m.size());
+  int tpc = 0, tpf = 0;
+  for (size_t i = 0; i < b->m.size(); ++i) {
+    pc[i] = tpc;
+    pf[i] = tpf;
+    tpc += tfan::persist_collide_tiles(b->m[i]->dp);
+    tpf += tfan::persist_fd_tiles(b->m[i]->dp);
+  }
+  b->tiles_pc = tpc;
+  b->tiles_pf = tpf;
   hipError_t e = hipMemcpyAsync(b->first_c, fc.data(), fc.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->first_f, ff.data(), ff.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->first_pc, pc.data(), pc.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->first_pf, pf.data(), pf.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("batch tables: ") + hipGetErrorString(e));
   return TFAN_OK;
@@ -734,6 +753,8 @@ int tfan_batch_create(const tfan_params* p, int32_t count, void* ws, size_t byte
   b->table = (tfan::BatchMember*)base;
   b->first_c = (int*)(base + align_up(count * sizeof(tfan::BatchMember)));
   b->first_f = (int*)((char*)b->first_c + align_up(count * sizeof(int)));
+  b->first_pc = (int*)((char*)b->first_f + align_up(count * sizeof(int)));
+  b->first_pf = (int*)((char*)b->first_pc + align_up(count * sizeof(int)));
   size_t off = batch_table_bytes(count);
   std::vector<tfan::BatchMember> host(count);
   for (int i = 0; i < count; ++i) {
@@ -813,6 +834,27 @@ int tfan_batch_step(tfan_batch* b, int64_t nsteps) {
       s->cur = nb;
       s->step += 1;
     }
+  }
+  return TFAN_OK;
+}
+
+int tfan_batch_step_persistent(tfan_batch* b, int64_t nsteps) {
+  if (!b) return bfail(nullptr, TFAN_EINVAL, "batch is NULL");
+  if (nsteps < 0 || nsteps > INT32_MAX) return bfail(b, TFAN_EINVAL, "step count must be in [0, 2^31)");
+  if (b->n_sub > tfan::kFusedMaxSub)
+    return bfail(b, TFAN_EINVAL, "the persistent launch takes n_sub <= 5 (all sub-steps of a step in one phase)");
+  if (nsteps == 0) return TFAN_OK;
+  hipError_t e = tfan::launch_batch_persistent(b->table, b->first_pc, b->first_pf, (int)b->m.size(), b->tiles_pc,
+                                               b->tiles_pf, (int)nsteps, b->cur, b->n_sub, b->pop16, &b->persist_grid,
+                                               b->stream);
+  if (e != hipSuccess) return bfail(b, TFAN_EHIP, std::string("persistent batch launch: ") + hipGetErrorString(e));
+  // one sub-step phase per step: the fields alternate with the populations
+  const int nb = (int)((b->cur + nsteps) % 2);
+  b->cur = nb;
+  b->step += nsteps;
+  for (tfan_sim* s : b->m) {
+    s->cur = nb;
+    s->step += nsteps;
   }
   return TFAN_OK;
 }
@@ -911,3 +953,5 @@ void tfan_batch_destroy(tfan_batch* b) {
 const char* tfan_batch_last_error(const tfan_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"
+
+extern "C" int tfan_batch_persistent_blocks(const tfan_batch* b) { return b ? b->persist_grid : 0; }

@@ -115,6 +115,15 @@ hipError_t launch_fields(const DevParams& P, DevState in, float* aux /*[6][n]: d
 hipError_t launch_diag(const DevParams& P, DevState in, const float* aux /*[6][n]*/,
                        double* partials, int nblocks, double* result, hipStream_t st);
 int diag_blocks(const DevParams& P);
+// The persistent batch launch: tiles of one member for its collision phase (256 x 4)
+// and its sub-step phase (split phi / Q kernel, 64 x 40 tiles); one cooperative
+// launch of nsteps steps over all members, buffers `cur` -> 1 - cur -> ...,
+// `subs` (1..kFusedMaxSub) sub-steps per step.  *grid_out receives the block count.
+int persist_collide_tiles(const DevParams& P);
+int persist_fd_tiles(const DevParams& P);
+hipError_t launch_batch_persistent(const BatchMember* mem, const int* first_c, const int* first_f, int count,
+                                   int tiles_c, int tiles_f, int nsteps, int cur, int subs, bool pop16, int* grid_out,
+                                   hipStream_t st);
 // State exchange [7][n] (phi, Qxx, Qxy, u_a, u_p): pack from phi, q [2][n] and the
 // velocity planes aux_u [4][n]; unpack the other way.
 hipError_t launch_pack_state(int n, const float* phi, const float* q, const float* aux_u, float* out,

@@ -5,6 +5,7 @@
 // are stored after collision and before streaming ("post-collision"), shifted by
 // -w_i rho0 so that the small deviations from rest keep float32 precision; the
 // next step streams them by pulling f_i(x) = f*_i(x - c_i).
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -221,11 +222,17 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
 // fluids, 64 x 8: 137 us).  Binary16: 128 x 4 with 256 threads (77 us; 64 x 8:
 // 79 us; 256 x 4 with 512 threads: 85 us).
 // NW (narrow): tiles of half that width with half the threads, for the autotuner.
-template <typename PT, bool NW = false> struct CollideTile {
+// NT > 0: blocks of NT threads on 256-site-wide tiles (the persistent batch kernel).
+template <typename PT, bool NW = false, int NT = 0> struct CollideTile {
   static constexpr bool F32 = sizeof(PT) == 4;
-  static constexpr int X = (F32 ? 256 : 128) >> (NW ? 1 : 0), THREADS = 2 * X;
+  static constexpr int X = NT ? 256 : (F32 ? 256 : 128) >> (NW ? 1 : 0), THREADS = NT ? NT : 2 * X;
   static constexpr int ROWS = THREADS / X;          // rows per pass of the block
   static constexpr int PX = X + 4, SX = X + 2;      // phi/Q staging halo 2, mu/stress halo 1
+  // LDS of a tile of SITES rows per thread: phi, Qxx, Qxy with halo 2; mu and four
+  // stress components with halo 1
+  template <int SITES> static constexpr int lds_bytes() {
+    return 4 * (3 * (ROWS * SITES + 4) * PX + 5 * (ROWS * SITES + 2) * SX);
+  }
 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
@@ -290,19 +297,29 @@ __device__ __forceinline__ float2 be_update(float2 q, float2 qe, float2 qw, floa
 }
 
 // Tiles of the collision kernel: X x (ROWS * SITES) sites, SITES rows per thread.
-template <typename PT, int SITES, bool NW = false> __host__ __device__ inline int collide_tiles(int nx, int ny) {
-  using T = CollideTile<PT, NW>;
+template <typename PT, int SITES, bool NW = false, int NT = 0>
+__host__ __device__ inline int collide_tiles(int nx, int ny) {
+  using T = CollideTile<PT, NW, NT>;
   return ((nx + T::X - 1) / T::X) * ((ny + T::ROWS * SITES - 1) / (T::ROWS * SITES));
 }
 
-template <bool FIELDS, typename PT, int CT_SITES, bool NW = false>
+// lds: CollideTile<PT, NW, NT>::lds_bytes<CT_SITES>() bytes of the caller's shared memory.
+template <bool FIELDS, typename PT, int CT_SITES, bool NW = false, int NT = 0>
 __device__ __forceinline__ void collide_tile(const DevParams& P, const DevState& in, void* __restrict__ fout,
-                                             float* __restrict__ uout, int tile) {
-  using T = CollideTile<PT, NW>;
+                                             float* __restrict__ uout, int tile, unsigned char* __restrict__ lds) {
+  using T = CollideTile<PT, NW, NT>;
   constexpr int CT_X = T::X, CT_THREADS = T::THREADS, CT_ROWS_PER_PASS = T::ROWS, PX = T::PX, SX = T::SX;
   constexpr int CT_Y = CT_ROWS_PER_PASS * CT_SITES, PY = CT_Y + 4, SY = CT_Y + 2;
-  __shared__ float sph[PY][PX], sqx[PY][PX], sqy[PY][PX];
-  __shared__ float smu[SY][SX], sxx[SY][SX], syy[SY][SX], ssy[SY][SX], san[SY][SX];
+  using PRow = float[PX];
+  using SRow = float[SX];
+  PRow* sph = reinterpret_cast<PRow*>(lds);
+  PRow* sqx = sph + PY;
+  PRow* sqy = sqx + PY;
+  SRow* smu = reinterpret_cast<SRow*>(sqy + PY);
+  SRow* sxx = smu + SY;
+  SRow* syy = sxx + SY;
+  SRow* ssy = syy + SY;
+  SRow* san = ssy + SY;
   const int nx = P.nx, ny = P.ny, n = P.n;
   const int gx = (nx + CT_X - 1) / CT_X;
   const int tx = threadIdx.x % CT_X, ty = threadIdx.x / CT_X;
@@ -405,9 +422,10 @@ template <bool FIELDS, typename PT, int SITES, bool NW>
 __global__ void __launch_bounds__((CollideTile<PT, NW>::THREADS)) k_collide(DevParams P, DevState in,
                                                                             void* __restrict__ fout,
                                                                             float* __restrict__ uout) {
+  __shared__ __align__(16) unsigned char lds[CollideTile<PT, NW>::template lds_bytes<SITES>()];
   const int tile = xcd_tile(collide_tiles<PT, SITES, NW>(P.nx, P.ny));
   if (tile < 0) return;  // whole workgroup, before any barrier
-  collide_tile<FIELDS, PT, SITES, NW>(P, in, fout, uout, tile);
+  collide_tile<FIELDS, PT, SITES, NW>(P, in, fout, uout, tile, lds);
 }
 
 // Member of a batch whose tile index range starts at `first` (ascending array).
@@ -424,12 +442,13 @@ template <typename PT, int SITES, bool NW>
 __global__ void __launch_bounds__((CollideTile<PT, NW>::THREADS)) k_collide_batch(const BatchMember* __restrict__ mem,
                                                                     const int* __restrict__ first, int count,
                                                                     int tiles, int cur) {
+  __shared__ __align__(16) unsigned char lds[CollideTile<PT, NW>::template lds_bytes<SITES>()];
   const int tile = xcd_tile(tiles);
   if (tile < 0) return;
   const int m = batch_member(first, count, tile);
   const DevParams P = mem[m].P;
   const DevState in = mem[m].st[cur];
-  collide_tile<false, PT, SITES, NW>(P, in, mem[m].st[1 - cur].f, mem[m].U, tile - first[m]);
+  collide_tile<false, PT, SITES, NW>(P, in, mem[m].st[1 - cur].f, mem[m].U, tile - first[m], lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1070,6 +1089,76 @@ __global__ void __launch_bounds__((PairBlock<TH, MS>::NT), 8) k_fd_pair_batch(co
   else q_block_tile<TH, MS>(P, mem[m].st[src], mem[m].st[1 - src], mem[m].U, tile - first[m], subs, lds);
 }
 
+// ---------------------------------------------------------------------------
+// One persistent launch for every member of a batch and every step: blocks of
+// 1024 threads (two per compute unit) loop over the steps; in each step they
+// take the collision tiles of all members (256 x 4 sites, one site per thread),
+// meet at a grid-wide barrier, take the split phi / Q sub-step tiles of all
+// members (64 x 40, all sub-steps of the step), and meet again.  The launch is
+// cooperative, so every block is resident and every block reaches every
+// barrier (the work loops may be empty, the barriers are not).  Each block owns
+// a contiguous range of tiles, ranges ordered so that the blocks of one XCD hold
+// neighbouring tiles.
+// ---------------------------------------------------------------------------
+constexpr int kPersistThreads = 1024;
+template <typename PT> struct Persist {
+  using CT = CollideTile<PT, false, kPersistThreads>;
+  static constexpr int CLDS = CT::template lds_bytes<1>();
+  static constexpr int FLDS = PairBlock<kSplitTile, kFusedMaxSub>::LDS;
+  static constexpr int LDS = CLDS > FLDS ? CLDS : FLDS;
+  static_assert(PairBlock<kSplitTile, kFusedMaxSub>::NT == kPersistThreads, "one block size for both phases");
+};
+
+__device__ __forceinline__ void persist_range(int items, int& lo, int& hi) {
+  const int G = (int)gridDim.x, b = (int)blockIdx.x;
+  const int logical = (b % kXcds) * (G / kXcds) + b / kXcds;  // G is a multiple of kXcds
+  const int per = (items + G - 1) / G;
+  lo = min(items, logical * per);
+  hi = min(items, lo + per);
+}
+
+// One block per compute unit (124 VGPRs, 4 waves per SIMD): forcing two blocks
+// (64 VGPRs) spills ~50 registers and was slower (sweep 0.66 against 0.57 ms per step).
+template <typename PT>
+__global__ void __launch_bounds__(kPersistThreads, 4) k_batch_persistent(const BatchMember* __restrict__ mem,
+                                                                         const int* __restrict__ first_c,
+                                                                         const int* __restrict__ first_f, int count,
+                                                                         int tiles_c, int tiles_f, int nsteps, int cur,
+                                                                         int subs) {
+  __shared__ __align__(16) unsigned char lds[Persist<PT>::LDS];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  int c0, c1, f0, f1;
+  persist_range(tiles_c, c0, c1);
+  persist_range(pair_items(tiles_f), f0, f1);
+  for (int step = 0; step < nsteps; ++step) {
+    for (int t = c0; t < c1; ++t) {
+      const int m = batch_member(first_c, count, t);
+      const DevParams P = mem[m].P;
+      collide_tile<false, PT, 1, false, kPersistThreads>(P, mem[m].st[cur], mem[m].st[1 - cur].f, mem[m].U,
+                                                         t - first_c[m], lds);
+      __syncthreads();
+    }
+    grid.sync();
+    for (int it = f0; it < f1; ++it) {
+      bool phi;
+      const int tile = pair_tile(it, tiles_f, phi);
+      if (tile >= 0) {
+        const int m = batch_member(first_f, count, tile);
+        const DevParams P = mem[m].P;
+        if (phi)
+          phi_block_tile<kSplitTile, kFusedMaxSub>(P, mem[m].st[cur], mem[m].st[1 - cur], mem[m].U,
+                                                   tile - first_f[m], subs, lds);
+        else
+          q_block_tile<kSplitTile, kFusedMaxSub>(P, mem[m].st[cur], mem[m].st[1 - cur], mem[m].U, tile - first_f[m],
+                                                 subs, lds);
+      }
+      __syncthreads();
+    }
+    grid.sync();
+    cur = 1 - cur;
+  }
+}
+
 // Post-collision populations whose pull gives f^eq(rho0, u) at every site:
 // stored f*_i(x) = f^eq_i(u(x + c_i)) - w_i rho0.
 template <typename PT>
@@ -1394,6 +1483,29 @@ hipError_t launch_fd_batch(const BatchMember* mem, const int* first, int count, 
 hipError_t launch_fields(const DevParams& P, DevState in, float* aux, hipStream_t st) {
   if (P.pop16) launch_collide_tiles<true, _Float16, 2, false>(P, in, nullptr, aux, st);
   else launch_collide_tiles<true, float, 2, false>(P, in, nullptr, aux, st);
+  return hipGetLastError();
+}
+
+int persist_collide_tiles(const DevParams& P) { return collide_tiles<float, 1, false, kPersistThreads>(P.nx, P.ny); }
+int persist_fd_tiles(const DevParams& P) { return fused_tiles<kSplitTile>(P.nx, P.ny); }
+
+hipError_t launch_batch_persistent(const BatchMember* mem, const int* first_c, const int* first_f, int count,
+                                   int tiles_c, int tiles_f, int nsteps, int cur, int subs, bool pop16, int* grid_out,
+                                   hipStream_t st) {
+  const void* fn = pop16 ? reinterpret_cast<const void*>(&k_batch_persistent<_Float16>)
+                         : reinterpret_cast<const void*>(&k_batch_persistent<float>);
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kPersistThreads, 0);
+  if (e != hipSuccess) return e;
+  const int grid = (per_cu * cus) / kXcds * kXcds;
+  if (grid < kXcds) return hipErrorInvalidConfiguration;
+  if (grid_out) *grid_out = grid;
+  void* args[] = {(void*)&mem, (void*)&first_c, (void*)&first_f, (void*)&count, (void*)&tiles_c,
+                  (void*)&tiles_f, (void*)&nsteps, (void*)&cur, (void*)&subs};
+  e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPersistThreads), args, 0, st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -161,3 +161,54 @@ def test_batch_autotune_and_errors(gpu):
     assert e.value.code == T.TFAN_EINVAL
     with pytest.raises(T.TfanError):
         b.init_fields(7, *[np.zeros((40, 40))] * 3)
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_persistent_launch_matches_per_phase_launches(gpu, storage):
+    """One persistent launch for all members and steps gives bitwise the states of
+    the per-phase launches, also when the two are interleaved (buffer parity)."""
+    from paper_2511_00445_amd import Batch
+    say(f"case: persistent batch launch, storage {storage}")
+    ms = [dict(m, p=dict(m["p"], storage=storage)) for m in _members()]
+    a, b = Batch([m["p"] for m in ms]), Batch([m["p"] for m in ms])
+    a.set_tuning(2, 165)
+    for i, m in enumerate(ms):
+        a.init_fields(i, **m["ic"])
+        b.init_fields(i, **m["ic"])
+    a.step(12)
+    b.step_persistent(5)
+    b.step(2)
+    b.step_persistent(5)
+    assert b.persistent_blocks() > 0 and b.persistent_blocks() % 8 == 0
+    for i in range(len(ms)):
+        ga, gb = a.get_fields(i), b.get_fields(i)
+        for k in ga:
+            assert np.array_equal(ga[k], gb[k]), (i, k)
+        assert b.diagnostics(i)["step"] == 12
+
+
+@pytest.mark.parametrize("n_sub", [1, 3])
+def test_persistent_launch_other_substep_counts(gpu, n_sub):
+    from paper_2511_00445_amd import Batch
+    say(f"case: persistent batch launch, n_sub {n_sub}")
+    ms = [dict(m, p=dict(m["p"], n_sub=n_sub)) for m in _members()]
+    a, b = Batch([m["p"] for m in ms]), Batch([m["p"] for m in ms])
+    for i, m in enumerate(ms):
+        a.init_fields(i, **m["ic"])
+        b.init_fields(i, **m["ic"])
+    a.step(7)
+    b.step_persistent(7)
+    for i in range(len(ms)):
+        assert np.array_equal(a.get_fields(i)["phi"], b.get_fields(i)["phi"])
+        assert np.array_equal(a.get_fields(i)["u_a"], b.get_fields(i)["u_a"])
+
+
+def test_persistent_launch_rejects_more_than_five_substeps(gpu):
+    import paper_2511_00445_amd as T
+    say("case: persistent batch launch, n_sub 6")
+    b = T.Batch([base_params(32, 24, n_sub=6), base_params(40, 40, n_sub=6)])
+    for i, (nx, ny) in enumerate(((32, 24), (40, 40))):
+        b.init_fields(i, **initial_fields(nx, ny, seed=i))
+    with pytest.raises(T.TfanError) as e:
+        b.step_persistent(1)
+    assert e.value.code == T.TFAN_EINVAL

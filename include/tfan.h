@@ -164,22 +164,30 @@ int tfan_get_state(tfan_sim* s, void* host, size_t bytes);
 int tfan_set_state(tfan_sim* s, const void* host, size_t bytes);
 
 /* Device-side state exchange (for the convolutional surrogate, tfan_cnn.h).
- * Layout [7][ny][nx] float32: phi, Qxx, Qxy, u_a (x, y), u_p (x, y);
- * tfan_exchange_bytes() = 7 nx ny 4 bytes.
+ * Layout [planes][ny][nx] float32, planes = 7: phi, Qxx, Qxy, u_a (x, y),
+ * u_p (x, y); planes = 9: the same, then rho_a - rho0, rho_p - rho0.
+ * tfan_exchange_bytes(s, planes) = planes nx ny 4 bytes (0 for other plane counts).
  * tfan_export_state writes the current state into dev_out; the velocities are
  * the ones tfan_get_fields returns (the step's own half-force velocity solve).
- * tfan_import_state sets phi and Q from dev_in and both population sets to
- * f^eq(rho0, u) of its velocities (density deviations restart at zero, as after
- * tfan_init_fields), and sets the step counter to `step` (>= 0).
+ * tfan_import_state sets phi and Q from dev_in and rebuilds both population sets
+ * at equilibrium so that the next step's velocities (the half-force solve with
+ * the implicit drag, under the forces of the imported phi and Q) are those of
+ * dev_in, with the densities of dev_in (planes = 9) or, with planes = 7, the
+ * densities of the populations the handle holds at the call (rho0 on a handle
+ * that has had no tfan_init_fields, tfan_set_state or import yet).  Exporting
+ * right after an import gives back dev_in up to float32 rounding; what is lost
+ * is the populations' non-equilibrium part.  It sets the step counter to `step`
+ * (>= 0).
  * The arrays are caller-owned device memory on the handle's GPU: a pointer the
  * HIP runtime does not know as a device allocation of that GPU gives
- * TFAN_EINVAL; fewer than tfan_exchange_bytes() bytes (the `bytes` argument, or
- * what is left of the allocation from the pointer on) give TFAN_ENOMEM.  Both
- * are enqueued on the solver's stream as kernels (no runtime copies) and do not
- * synchronise; the arrays must stay valid until the stream reaches them. */
-size_t tfan_exchange_bytes(const tfan_sim* s);
-int tfan_export_state(tfan_sim* s, float* dev_out, size_t bytes);
-int tfan_import_state(tfan_sim* s, const float* dev_in, size_t bytes, int64_t step);
+ * TFAN_EINVAL, and so does a plane count other than 7 or 9; fewer than
+ * tfan_exchange_bytes(s, planes) bytes (the `bytes` argument, or what is left of
+ * the allocation from the pointer on) give TFAN_ENOMEM.  Both are enqueued on the
+ * solver's stream as kernels (no runtime copies) and do not synchronise; the
+ * arrays must stay valid until the stream reaches them. */
+size_t tfan_exchange_bytes(const tfan_sim* s, int32_t planes);
+int tfan_export_state(tfan_sim* s, float* dev_out, size_t bytes, int32_t planes);
+int tfan_import_state(tfan_sim* s, const float* dev_in, size_t bytes, int32_t planes, int64_t step);
 
 /* Wait for the handle's stream; reports execution errors. */
 int tfan_sync(tfan_sim* s);

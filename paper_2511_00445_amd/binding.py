@@ -96,9 +96,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "tfan_batch_destroy": (None, [_vp]),
         "tfan_batch_last_error": (ctypes.c_char_p, [_vp]),
         "tfan_kernel_name": (ctypes.c_char_p, [ctypes.c_int]),
-        "tfan_exchange_bytes": (ctypes.c_size_t, [_vp]),
-        "tfan_export_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
-        "tfan_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int64]),
+        "tfan_exchange_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int32]),
+        "tfan_export_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32]),
+        "tfan_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64]),
         "tfan_cnn_param_count": (ctypes.c_int64, []),
         "tfan_cnn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                                        ctypes.c_int32]),
@@ -172,6 +172,14 @@ def _check_dev(t, shape=None):
         raise TfanError(TFAN_EINVAL, "expected a contiguous float32 device tensor")
     if shape is not None and tuple(t.shape[-len(shape):]) != tuple(shape):
         raise TfanError(TFAN_EINVAL, f"expected trailing shape {shape}, got {tuple(t.shape)}")
+
+
+def _exchange_planes(t, ny, nx) -> int:
+    """Plane count (7 or 9) of a state exchange tensor [planes][ny][nx]."""
+    _check_dev(t)
+    if t.dim() != 3 or tuple(t.shape[1:]) != (ny, nx) or t.shape[0] not in (7, 9):
+        raise TfanError(TFAN_EINVAL, f"expected a [7 or 9][{ny}][{nx}] tensor, got {tuple(t.shape)}")
+    return int(t.shape[0])
 
 
 def _f64(a, shape):
@@ -264,14 +272,18 @@ class Sim:
         self._check(self.lib.tfan_sync(self._handle))
 
     def export_state(self, out):
-        """Write (phi, Qxx, Qxy, u_a, u_p) as float32 [7][ny][nx] into the device tensor out."""
-        _check_dev(out, (7, self.ny, self.nx))
-        self._check(self.lib.tfan_export_state(self._handle, _vp(out.data_ptr()), out.numel() * 4))
+        """Write (phi, Qxx, Qxy, u_a, u_p) as float32 [7][ny][nx], or with the two density
+        deviations as [9][ny][nx], into the device tensor out (the plane count is its
+        shape's)."""
+        planes = _exchange_planes(out, self.ny, self.nx)
+        self._check(self.lib.tfan_export_state(self._handle, _vp(out.data_ptr()), out.numel() * 4, planes))
 
     def import_state(self, x, step: int):
-        """Set phi, Q and equilibrium populations from the device tensor x [7][ny][nx]."""
-        _check_dev(x, (7, self.ny, self.nx))
-        self._check(self.lib.tfan_import_state(self._handle, _vp(x.data_ptr()), x.numel() * 4, int(step)))
+        """Set phi, Q and equilibrium populations giving back the velocities of the
+        device tensor x: [7][ny][nx] keeps the handle's densities, [9][ny][nx] takes its
+        own."""
+        planes = _exchange_planes(x, self.ny, self.nx)
+        self._check(self.lib.tfan_import_state(self._handle, _vp(x.data_ptr()), x.numel() * 4, planes, int(step)))
 
     def step_count(self) -> int:
         return int(self.lib.tfan_step_count(self._handle))

@@ -31,6 +31,7 @@ struct tfan_sim {
   double* partials = nullptr;          // [diag blocks][kDiagSlots]
   double* result = nullptr;            // [kDiagSlots]
   int cur = 0;                         // index of the buffers holding the state
+  bool has_state = false;              // set by init_fields, set_state and import_state
   tfan::Tuning tune;                   // launch shape of the hot kernels
   int64_t step = 0;
   std::string err;
@@ -303,6 +304,7 @@ int tfan_init_fields(tfan_sim* s, const double* phi, const double* qxx, const do
     if (e != hipSuccess) return hip_fail(s, e, "init kernel launch");
   }
   s->step = 0;
+  s->has_state = true;
   return sync_stream(s, "init_fields");
 }
 
@@ -448,6 +450,7 @@ int tfan_set_state(tfan_sim* s, const void* host, size_t bytes) {
     e = hipMemcpyAsync(s->q[0], h + fb + n * sizeof(float), 2 * n * sizeof(float), hipMemcpyHostToDevice,
                        s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state");
+  s->has_state = true;
   s->step = step;
   return sync_stream(s, "set_state");
 }
@@ -483,13 +486,16 @@ static int check_device_range(tfan_sim* s, const void* ptr, size_t bytes, const 
   return TFAN_OK;
 }
 
-size_t tfan_exchange_bytes(const tfan_sim* s) { return s ? 7 * (size_t)s->dp.n * sizeof(float) : 0; }
+size_t tfan_exchange_bytes(const tfan_sim* s, int32_t planes) {
+  return s && (planes == 7 || planes == 9) ? (size_t)planes * (size_t)s->dp.n * sizeof(float) : 0;
+}
 
-int tfan_export_state(tfan_sim* s, float* out, size_t bytes) {
+int tfan_export_state(tfan_sim* s, float* out, size_t bytes, int32_t planes) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (planes != 7 && planes != 9) return fail(s, TFAN_EINVAL, "planes must be 7 or 9");
   if (!out) return fail(s, TFAN_EINVAL, "output array is NULL");
-  const size_t need = tfan_exchange_bytes(s);
-  if (bytes < need) return fail(s, TFAN_ENOMEM, "output array smaller than 7 planes of the grid");
+  const size_t need = tfan_exchange_bytes(s, planes);
+  if (bytes < need) return fail(s, TFAN_ENOMEM, "output array smaller than `planes` planes of the grid");
   if (int rc = check_device_range(s, out, need, "output array")) return rc;
   const int n = s->dp.n;
   {
@@ -497,28 +503,34 @@ int tfan_export_state(tfan_sim* s, float* out, size_t bytes) {
     hipError_t e = tfan::launch_fields(s->dp, state_of(s, s->cur), s->aux, s->stream);
     if (e != hipSuccess) return hip_fail(s, e, "fields kernel launch");
   }
-  // aux holds [drho_a, drho_p, u_a (2), u_p (2)]
-  hipError_t e = tfan::launch_pack_state(n, s->phi[s->cur], s->q[s->cur], s->aux + 2 * (size_t)n, out, s->stream);
+  hipError_t e = tfan::launch_pack_state(n, planes, s->phi[s->cur], s->q[s->cur], s->aux, out, s->stream);
   return e == hipSuccess ? TFAN_OK : hip_fail(s, e, "state export launch");
 }
 
-int tfan_import_state(tfan_sim* s, const float* in, size_t bytes, int64_t step) {
+int tfan_import_state(tfan_sim* s, const float* in, size_t bytes, int32_t planes, int64_t step) {
   if (!s) return fail(nullptr, TFAN_EINVAL, "handle is NULL");
+  if (planes != 7 && planes != 9) return fail(s, TFAN_EINVAL, "planes must be 7 or 9");
   if (!in) return fail(s, TFAN_EINVAL, "input array is NULL");
   if (step < 0) return fail(s, TFAN_EINVAL, "step must be >= 0");
-  const size_t need = tfan_exchange_bytes(s);
-  if (bytes < need) return fail(s, TFAN_ENOMEM, "input array smaller than 7 planes of the grid");
+  const size_t need = tfan_exchange_bytes(s, planes);
+  if (bytes < need) return fail(s, TFAN_ENOMEM, "input array smaller than `planes` planes of the grid");
   if (int rc = check_device_range(s, in, need, "input array")) return rc;
   const int n = s->dp.n;
-  s->cur = 0;
-  hipError_t e = tfan::launch_unpack_state(n, in, s->phi[0], s->q[0], s->aux, s->stream);
+  // phi, Q go to the spare buffers, the velocities (and densities) to aux; the
+  // populations are rebuilt in the spare buffer, which becomes the current state
+  const int nxt = s->cur ^ 1;
+  hipError_t e = tfan::launch_unpack_state(n, planes, in, s->phi[nxt], s->q[nxt], s->aux, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "state import launch");
   {
     TimedLaunch t(s, tfan::K_INIT);
-    e = tfan::launch_init(s->dp, s->aux, state_of(s, 0), s->stream);
-    if (e != hipSuccess) return hip_fail(s, e, "init kernel launch");
+    const void* keep = planes == 7 && s->has_state ? s->f[s->cur] : nullptr;
+    const float* drho = planes == 9 ? s->aux + 4 * (size_t)n : nullptr;
+    e = tfan::launch_import(s->dp, keep, state_of(s, nxt), s->aux, drho, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "import kernel launch");
   }
+  s->cur = nxt;
   s->step = step;
+  s->has_state = true;
   return TFAN_OK;
 }
 

@@ -95,6 +95,12 @@ enum KernelId { K_COLLIDE = 0, K_FD, K_INIT, K_FIELDS, K_DIAG, K_FDN, K_COUNT };
 // Launchers (return hipGetLastError() after the launch).
 hipError_t launch_init(const DevParams& P, const float* aux_u /*[4][n]*/, DevState out,
                        hipStream_t st);
+// Populations of out.f reproducing the velocities u_in ([4][n]: u_a,x, u_a,y, u_p,x,
+// u_p,y) at the next step, with the forces of out.phi, out.q, and the density
+// deviations drho ([2][n]) or else those of f_old (neither: rho0).  out.f must not
+// alias f_old.
+hipError_t launch_import(const DevParams& P, const void* f_old, DevState out, const float* u_in, const float* drho,
+                         hipStream_t st);
 // e0, e1 (optional): timing events recorded at the kernel's start and end.
 hipError_t launch_collide(const DevParams& P, DevState in, void* f_out, float* u_out /*[4][n]*/,
                           Tuning tn, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
@@ -124,10 +130,12 @@ int persist_fd_tiles(const DevParams& P);
 hipError_t launch_batch_persistent(const BatchMember* mem, const int* first_c, const int* first_f, int count,
                                    int tiles_c, int tiles_f, int nsteps, int cur, int subs, bool pop16, int* grid_out,
                                    hipStream_t st);
-// State exchange [7][n] (phi, Qxx, Qxy, u_a, u_p): pack from phi, q [2][n] and the
-// velocity planes aux_u [4][n]; unpack the other way.
-hipError_t launch_pack_state(int n, const float* phi, const float* q, const float* aux_u, float* out,
+// State exchange [planes][n], planes 7 (phi, Qxx, Qxy, u_a, u_p) or 9 (and the density
+// deviations of both fluids).  Pack from phi, q [2][n] and aux as the fields kernel
+// leaves it ([drho_a, drho_p, u_a (2), u_p (2)]); unpack to phi, q, the velocities in
+// aux planes 0..3 and the density deviations in aux planes 4..5.
+hipError_t launch_pack_state(int n, int planes, const float* phi, const float* q, const float* aux, float* out,
                              hipStream_t st);
-hipError_t launch_unpack_state(int n, const float* in, float* phi, float* q, float* aux_u, hipStream_t st);
+hipError_t launch_unpack_state(int n, int planes, const float* in, float* phi, float* q, float* aux, hipStream_t st);
 
 }  // namespace tfan

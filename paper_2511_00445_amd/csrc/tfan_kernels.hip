@@ -152,9 +152,12 @@ struct SiteStencil {
 // one site, with fa, fp its pulled populations (replaced by post-collision values).
 // uo receives (u_a,x, u_a,y, u_c,x, u_c,y) when colliding, else the density
 // deviations and velocities (rho_a - rho0, rho_p - rho0, u_a,x, u_a,y, u_p,x, u_p,y).
-template <bool COLLIDE>
-__device__ __forceinline__ void site_update(const DevParams& P, float fa[9], float fp[9], const SiteStencil& t,
-                                            float uo[6]) {
+// Non-drag forces on the two fluids at one site (the drag is implicit in the
+// velocity solve) and the volume fractions c1 = (1 + phi)/2, c2 = (1 - phi)/2.
+struct SiteForce {
+  float ax, ay, px, py, c1, c2;
+};
+__device__ __forceinline__ SiteForce site_forces(const SiteStencil& t) {
   // F_i = d_j sigma_ij with sigma_xy = s + a, sigma_yx = s - a
   const float Fx = 0.5f * (t.xxE - t.xxW) + 0.5f * ((t.sN + t.aN) - (t.sS + t.aS));
   const float Fy = 0.5f * ((t.sE - t.aE) - (t.sW - t.aW)) + 0.5f * (t.yyN - t.yyS);
@@ -167,8 +170,15 @@ __device__ __forceinline__ void site_update(const DevParams& P, float fa[9], flo
   // the form evaluated here (the same value, fewer roundings).
   const float fchx = 0.5f * (t.phE * (t.mu - t.muE) - t.phW * (t.mu - t.muW));
   const float fchy = 0.5f * (t.phN * (t.mu - t.muN) - t.phS * (t.mu - t.muS));
-  const float Gax = Fx + c1 * fchx, Gay = Fy + c1 * fchy;
-  const float Gpx = c2 * fchx, Gpy = c2 * fchy;
+  return SiteForce{Fx + c1 * fchx, Fy + c1 * fchy, c2 * fchx, c2 * fchy, c1, c2};
+}
+
+template <bool COLLIDE>
+__device__ __forceinline__ void site_update(const DevParams& P, float fa[9], float fp[9], const SiteStencil& t,
+                                            float uo[6]) {
+  const SiteForce G = site_forces(t);
+  const float c1 = G.c1, c2 = G.c2;
+  const float Gax = G.ax, Gay = G.ay, Gpx = G.px, Gpy = G.py;
   float dra = 0.f, mxa = 0.f, mya = 0.f, drp = 0.f, mxp = 0.f, myp = 0.f;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -1182,29 +1192,99 @@ __global__ void __launch_bounds__(256) k_init(DevParams P, const float* __restri
   }
 }
 
-// State exchange layout [7][n]: phi, Qxx, Qxy, u_a,x, u_a,y, u_p,x, u_p,y.  The
-// velocities come from (pack) or go to (unpack) planes 2..5 / 0..3 of aux.
-__global__ void __launch_bounds__(256) k_pack_state(int n, const float* __restrict__ phi,
-                                                    const float* __restrict__ q,
-                                                    const float* __restrict__ aux_u,
+// Populations that reproduce a given macroscopic state at the next step.  For
+// every site: the densities are the given deviations drho ([2][n]) or else those of
+// the current populations f_old (pulled as the next step would pull them), the
+// forces those of the given phi and Q, and the
+// momenta m solve the velocity equations of the step for the given velocities,
+// m_a = (rho_a + g) u_a - g u_p - G_a / 2 and m_p = (rho_p + g) u_p - g u_a - G_p / 2,
+// so that the next step's Guo velocities equal u.  The pull of site x then sees
+// f^eq(rho, m / rho): stored f*_i(x - c_i) = f^eq_i(x) - w_i rho0 in f_out (which
+// must not alias f_old).  Neither drho nor f_old: densities rho0.  One thread per
+// site; stencils read from global memory.
+template <typename PT>
+__global__ void __launch_bounds__(256) k_import(DevParams P, const void* __restrict__ f_old,
+                                                const float* __restrict__ phi, const float* __restrict__ q,
+                                                const float* __restrict__ u_in, const float* __restrict__ drho,
+                                                void* __restrict__ f_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= P.nx || y >= P.ny) return;
+  const int nx = P.nx, ny = P.ny, n = P.n;
+  auto at = [&](int dx, int dy) { return wrap_any(y + dy, ny) * nx + wrap_any(x + dx, nx); };
+  auto mu_at = [&](int dx, int dy) {
+    return chem_pot(phi[at(dx, dy)], phi[at(dx + 1, dy)], phi[at(dx - 1, dy)], phi[at(dx, dy + 1)],
+                    phi[at(dx, dy - 1)], P);
+  };
+  auto stress_at = [&](int dx, int dy) {
+    const int c = at(dx, dy), e = at(dx + 1, dy), w = at(dx - 1, dy), nn = at(dx, dy + 1), ss = at(dx, dy - 1);
+    return nematic_stress(q[c], q[n + c], q[e], q[n + e], q[w], q[n + w], q[nn], q[n + nn], q[ss], q[n + ss],
+                          0.5f * (1.f + phi[c]), P);
+  };
+  const Stress sE = stress_at(1, 0), sW = stress_at(-1, 0), sN = stress_at(0, 1), sS = stress_at(0, -1);
+  const SiteStencil t = {sE.xx, sW.xx, sN.yy, sS.yy, sE.s, sW.s, sN.s, sS.s, sE.a, sW.a, sN.a, sS.a,
+                         mu_at(1, 0), mu_at(-1, 0), mu_at(0, 1), mu_at(0, -1), phi[at(0, 0)],
+                         mu_at(0, 0), phi[at(1, 0)], phi[at(-1, 0)], phi[at(0, 1)], phi[at(0, -1)]};
+  const SiteForce G = site_forces(t);
+  const int idx = y * nx + x;
+  float dra = 0.f, drp = 0.f;  // rho0 without densities given or populations to keep
+  if (drho) {
+    dra = drho[idx];
+    drp = drho[n + idx];
+  } else if (f_old) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float a, b;
+      pop_ld2<PT>(f_old, i, (size_t)n, (size_t)at(-CX[i], -CY[i]), a, b);
+      dra += a;
+      drp += b;
+    }
+  }
+  const float rho_a = P.rho0 + dra, rho_p = P.rho0 + drp;
+  const float g = 0.5f * P.gamma * G.c1 * G.c2;
+  const float uax = u_in[idx], uay = u_in[n + idx], upx = u_in[2 * n + idx], upy = u_in[3 * n + idx];
+  const float vax = ((rho_a + g) * uax - g * upx - 0.5f * G.ax) / rho_a;
+  const float vay = ((rho_a + g) * uay - g * upy - 0.5f * G.ay) / rho_a;
+  const float vpx = ((rho_p + g) * upx - g * uax - 0.5f * G.px) / rho_p;
+  const float vpy = ((rho_p + g) * upy - g * uay - 0.5f * G.py) / rho_p;
+  const float ua15 = 1.5f * (vax * vax + vay * vay), up15 = 1.5f * (vpx * vpx + vpy * vpy);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const float ca = (float)CX[i] * vax + (float)CY[i] * vay;
+    const float cp = (float)CX[i] * vpx + (float)CY[i] * vpy;
+    pop_st2<PT>(f_out, i, (size_t)n, (size_t)at(-CX[i], -CY[i]), WT[i] * (dra + rho_a * (ca * (3.f + 4.5f * ca) - ua15)),
+                WT[i] * (drp + rho_p * (cp * (3.f + 4.5f * cp) - up15)));
+  }
+}
+
+// State exchange layout [planes][n], planes 7 or 9: phi, Qxx, Qxy, u_a,x, u_a,y,
+// u_p,x, u_p,y, then (9) rho_a - rho0, rho_p - rho0.  Pack reads the velocities and
+// densities from aux as the fields kernel leaves it, [drho_a, drho_p, u_a (2), u_p (2)];
+// unpack writes the velocities to aux planes 0..3 and the densities to planes 4..5.
+__global__ void __launch_bounds__(256) k_pack_state(int n, int planes, const float* __restrict__ phi,
+                                                    const float* __restrict__ q, const float* __restrict__ aux,
                                                     float* __restrict__ out) {
-  const size_t total = 7 * (size_t)n;
+  const size_t total = (size_t)planes * n;
   for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
     const size_t plane = j / (size_t)n, i = j - plane * (size_t)n;
-    const float v = plane == 0 ? phi[i] : plane < 3 ? q[(plane - 1) * (size_t)n + i] : aux_u[(plane - 3) * (size_t)n + i];
+    const float v = plane == 0  ? phi[i]
+                    : plane < 3 ? q[(plane - 1) * (size_t)n + i]
+                    : plane < 7 ? aux[(plane - 1) * (size_t)n + i]
+                                : aux[(plane - 7) * (size_t)n + i];
     out[j] = v;
   }
 }
 
-__global__ void __launch_bounds__(256) k_unpack_state(int n, const float* __restrict__ in, float* __restrict__ phi,
-                                                      float* __restrict__ q, float* __restrict__ aux_u) {
-  const size_t total = 7 * (size_t)n;
+__global__ void __launch_bounds__(256) k_unpack_state(int n, int planes, const float* __restrict__ in,
+                                                      float* __restrict__ phi, float* __restrict__ q,
+                                                      float* __restrict__ aux) {
+  const size_t total = (size_t)planes * n;
   for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
     const size_t plane = j / (size_t)n, i = j - plane * (size_t)n;
     const float v = in[j];
     if (plane == 0) phi[i] = v;
     else if (plane < 3) q[(plane - 1) * (size_t)n + i] = v;
-    else aux_u[(plane - 3) * (size_t)n + i] = v;
+    else aux[(plane - 3) * (size_t)n + i] = v;
   }
 }
 
@@ -1329,6 +1409,16 @@ inline dim3 grid2d(const DevParams& P, dim3 blk) {
 int diag_blocks(const DevParams& P) {
   const int b = (P.n + kDiagThreads - 1) / kDiagThreads;
   return b < kDiagMaxBlocks ? b : kDiagMaxBlocks;
+}
+
+hipError_t launch_import(const DevParams& P, const void* f_old, DevState out, const float* u_in, const float* drho,
+                         hipStream_t st) {
+  const dim3 blk(64, 4);
+  if (P.pop16)
+    hipLaunchKernelGGL(k_import<_Float16>, grid2d(P, blk), blk, 0, st, P, f_old, out.phi, out.q, u_in, drho, out.f);
+  else
+    hipLaunchKernelGGL(k_import<float>, grid2d(P, blk), blk, 0, st, P, f_old, out.phi, out.q, u_in, drho, out.f);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(const DevParams& P, const float* aux_u, DevState out, hipStream_t st) {
@@ -1509,18 +1599,18 @@ hipError_t launch_batch_persistent(const BatchMember* mem, const int* first_c, c
   return hipGetLastError();
 }
 
-hipError_t launch_pack_state(int n, const float* phi, const float* q, const float* aux_u, float* out,
+hipError_t launch_pack_state(int n, int planes, const float* phi, const float* q, const float* aux, float* out,
                              hipStream_t st) {
-  const size_t total = 7 * (size_t)n;
+  const size_t total = (size_t)planes * n;
   const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_pack_state, dim3(blocks), dim3(256), 0, st, n, phi, q, aux_u, out);
+  hipLaunchKernelGGL(k_pack_state, dim3(blocks), dim3(256), 0, st, n, planes, phi, q, aux, out);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack_state(int n, const float* in, float* phi, float* q, float* aux_u, hipStream_t st) {
-  const size_t total = 7 * (size_t)n;
+hipError_t launch_unpack_state(int n, int planes, const float* in, float* phi, float* q, float* aux, hipStream_t st) {
+  const size_t total = (size_t)planes * n;
   const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_unpack_state, dim3(blocks), dim3(256), 0, st, n, in, phi, q, aux_u);
+  hipLaunchKernelGGL(k_unpack_state, dim3(blocks), dim3(256), 0, st, n, planes, in, phi, q, aux);
   return hipGetLastError();
 }
 

@@ -146,7 +146,7 @@ class SurrogateRun:
     """A solver advanced by surrogate calls, checked against itself, with rollback."""
 
     def __init__(self, sim: Sim, net: Cnn, k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2,
-                 hold: int = 10, channels=(0, 1, 2), relax: int = 0):
+                 hold: int = 10, channels=(0, 1, 2), relax: int = 0, densities: str = "reset"):
         import torch
         if net.batch != 1 or (net.ny, net.nx) != (sim.ny, sim.nx):
             raise ValueError("the network must take one sample of the solver's grid")
@@ -156,11 +156,23 @@ class SurrogateRun:
         self.relax = int(relax)  # solver steps after every call: a call covers k + relax steps
         if self.relax < 0:
             raise ValueError("relax must be >= 0")
+        # densities after a network jump (the network predicts none): "reset" to rho0,
+        # or "keep" those the solver held before the jump.  Kept densities are exact
+        # for the solver's own states, but over hundreds of chained jumps they drift
+        # (a growing low-density region) and phi overshoots grow until a relax span
+        # diverges; the checks then roll back, so "keep" is slower and noisier.
+        if densities not in ("keep", "reset"):
+            raise ValueError("densities must be 'keep' or 'reset'")
+        self.densities = densities
         shape = (1, 7, sim.ny, sim.nx)
         self.x = torch.empty(shape, dtype=torch.float32, device="cuda")
         self.xp = torch.empty_like(self.x)
         self.xs = torch.empty_like(self.x)
-        self.good = torch.empty_like(self.x)
+        # jump target with zero density planes, for densities = "reset"
+        self.x9 = torch.zeros((9, sim.ny, sim.nx), dtype=torch.float32, device="cuda") if densities == "reset" else None
+        # last checked state with its densities: a rollback restores all but the
+        # populations' non-equilibrium part
+        self.good = torch.empty((9, sim.ny, sim.nx), dtype=torch.float32, device="cuda")
         self.good_step = None
         self.since_check = 0
         self.surrogate_calls = self.solver_calls = self.checks = self.fallbacks = 0
@@ -168,7 +180,7 @@ class SurrogateRun:
         self.errors = []  # (step, relative L2 error) of every check
 
     def _mark_good(self):
-        self.sim.export_state(self.good[0])
+        self.sim.export_state(self.good)
         self.good_step = self.sim.step_count()
         self.since_check = 0
 
@@ -188,12 +200,12 @@ class SurrogateRun:
                     self._mark_good()
                 continue
             self.sim.export_state(self.x[0])
-            self.net.forward(self.x, self.xp)
+            self.net.forward(self.x, self.x9[None, :7] if self.x9 is not None else self.xp)
             self.since_check += 1
             if self.since_check == self.check_every:
                 self.sim.step(self.k)
                 self.sim.export_state(self.xs[0])
-                c = self.net.compare(self.xp, self.xs)
+                c = self.net.compare(self.x9[None, :7] if self.x9 is not None else self.xp, self.xs)
                 err = float(np.sqrt(c[self.channels, 0].sum() / c[self.channels, 1].sum()))
                 self.errors.append((self.sim.step_count(), err))
                 self.checks += 1
@@ -206,11 +218,11 @@ class SurrogateRun:
                     # restore the last checked state; redo the span with the solver
                     self.fallbacks += 1
                     span = (self.sim.step_count() - self.good_step) // (self.k + self.relax) + 1
-                    self.sim.import_state(self.good[0], self.good_step)
+                    self.sim.import_state(self.good, self.good_step)
                     self.plain_left = span + self.hold
                     self.since_check = 0
             else:
-                self.sim.import_state(self.xp[0], self.sim.step_count() + self.k)
+                self.sim.import_state(self.x9 if self.x9 is not None else self.xp[0], self.sim.step_count() + self.k)
                 self.surrogate_calls += 1
                 if self.relax:  # the solver smooths what the jump leaves at the grid scale
                     self.sim.step(self.relax)
@@ -246,11 +258,17 @@ def train_surrogate(params: dict, seeds, t0: int, t1: int, steps: int, batch: in
 
 def deploy_compare(params: dict, seed: int, theta, s_in, s_out, t_start: int, t_end: int, every: int,
                    k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2, hold: int = 10, relax: int = 0,
-                   log=None):
+                   densities: str = "reset", noise_floor: bool = False, log=None):
     """The plain solver and the surrogate-accelerated run from the same state at
     t_start to t_end.  Domain length L(t) every `every` steps (host analysis of phi,
     outside the timed spans).  Returns a dict of the two L records, the stepping
-    wall times, simulated steps per second and the maximum relative L deviation."""
+    wall times, simulated steps per second and the maximum relative L deviation.
+    noise_floor: also run the plain solver from the same state after one export /
+    import round trip (the reconstruction the surrogate applies, without the
+    network: only the populations' non-equilibrium part is lost) and return its L
+    record and largest relative deviation, the chaotic spread against which the
+    surrogate's deviation is read."""
+    import torch
     from .analysis import domain_length
     ny, nx = int(params["ny"]), int(params["nx"])
     sim = Sim(params)
@@ -258,25 +276,38 @@ def deploy_compare(params: dict, seed: int, theta, s_in, s_out, t_start: int, t_
     sim.step(t_start)
     sim.sync()
     start = sim.get_state()
+    samples = (t_end - t_start) // every
 
     def phi_length():
         f = sim.get_fields()
         return domain_length(f["phi"])
 
     plain_L, plain_s = [], 0.0
-    for _ in range((t_end - t_start) // every):
+    for _ in range(samples):
         _, dt = timed(sim.step, every)
         plain_s += dt
         plain_L.append(phi_length())
     if sim.diagnostics()["status"] != 0:
         raise RuntimeError("plain run became unhealthy")
+    extra = {}
+    if noise_floor:
+        sim.set_state(start)
+        x = torch.empty((7, ny, nx), dtype=torch.float32, device="cuda")
+        sim.export_state(x)
+        sim.import_state(x, t_start)
+        floor_L = []
+        for _ in range(samples):
+            sim.step(every)
+            floor_L.append(phi_length())
+        extra = dict(L_round_trip=floor_L,
+                     max_L_dev_round_trip=float(np.max(np.abs(np.array(floor_L) / np.array(plain_L) - 1))))
     sim.set_state(start)
     net = Cnn(1, ny, nx)
     net.set_params(theta)
     net.set_scales(s_in, s_out)
-    run = SurrogateRun(sim, net, k=k, check_every=check_every, tol=tol, hold=hold, relax=relax)
+    run = SurrogateRun(sim, net, k=k, check_every=check_every, tol=tol, hold=hold, relax=relax, densities=densities)
     sur_L, sur_s = [], 0.0
-    for _ in range((t_end - t_start) // every):
+    for _ in range(samples):
         _, dt = timed(run.advance, every)
         sur_s += dt
         sur_L.append(phi_length())
@@ -288,7 +319,7 @@ def deploy_compare(params: dict, seed: int, theta, s_in, s_out, t_start: int, t_
     out = dict(t=list(range(t_start + every, t_end + 1, every)), L_plain=plain_L, L_surrogate=sur_L,
                max_L_dev=float(dev.max()), plain_seconds=plain_s, surrogate_seconds=sur_s,
                plain_steps_per_s=span / plain_s, surrogate_steps_per_s=span / sur_s, speedup=plain_s / sur_s,
-               status=status, **run.summary())
+               status=status, **extra, **run.summary())
     net.close()
     sim.close()
     return out

@@ -119,12 +119,17 @@ static void handle_checks() {
   const int64_t neg = -5;
   std::memcpy(st.data(), &neg, sizeof neg);
   EXPECT(tfan_set_state(s, st.data(), sb) == TFAN_EINVAL);
-  EXPECT(tfan_exchange_bytes(s) == 7 * n * 4);
-  EXPECT(tfan_export_state(s, nullptr, 7 * n * 4) == TFAN_EINVAL);
-  std::vector<float> xs(7 * n);
-  EXPECT(tfan_export_state(s, xs.data(), 7 * n * 4 - 4) == TFAN_ENOMEM);
-  EXPECT(tfan_import_state(s, xs.data(), 7 * n * 4, -1) == TFAN_EINVAL);
-  EXPECT(tfan_import_state(s, xs.data(), 3, 0) == TFAN_ENOMEM);
+  EXPECT(tfan_exchange_bytes(s, 7) == 7 * n * 4);
+  EXPECT(tfan_exchange_bytes(s, 9) == 9 * n * 4);
+  EXPECT(tfan_exchange_bytes(s, 8) == 0);
+  EXPECT(tfan_export_state(s, nullptr, 7 * n * 4, 7) == TFAN_EINVAL);
+  std::vector<float> xs(9 * n);
+  EXPECT(tfan_export_state(s, xs.data(), 9 * n * 4, 8) == TFAN_EINVAL);
+  EXPECT(tfan_export_state(s, xs.data(), 7 * n * 4 - 4, 7) == TFAN_ENOMEM);
+  EXPECT(tfan_export_state(s, xs.data(), 7 * n * 4, 9) == TFAN_ENOMEM);
+  EXPECT(tfan_import_state(s, xs.data(), 7 * n * 4, 7, -1) == TFAN_EINVAL);
+  EXPECT(tfan_import_state(s, xs.data(), 9 * n * 4, 0, 0) == TFAN_EINVAL);
+  EXPECT(tfan_import_state(s, xs.data(), 3, 7, 0) == TFAN_ENOMEM);
   EXPECT(tfan_kernel_timing(s, -1) == TFAN_EINVAL);
   EXPECT(tfan_kernel_timing(s, (int64_t(1) << 20) + 1) == TFAN_EINVAL);
   EXPECT(tfan_step_count(s) == 0);
@@ -140,10 +145,11 @@ static void null_handles() {
   EXPECT(tfan_get_fields(nullptr, &d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr) == TFAN_EINVAL);
   EXPECT(tfan_diagnostics(nullptr, &dg) == TFAN_EINVAL);
   EXPECT(tfan_sync(nullptr) == TFAN_EINVAL);
-  EXPECT(tfan_state_bytes(nullptr) == 0 && tfan_exchange_bytes(nullptr) == 0);
+  EXPECT(tfan_state_bytes(nullptr) == 0 && tfan_exchange_bytes(nullptr, 7) == 0);
   EXPECT(tfan_step_count(nullptr) == -1);
   EXPECT(tfan_set_tuning(nullptr, 1, 165) == TFAN_EINVAL);
-  EXPECT(tfan_export_state(nullptr, nullptr, 0) == TFAN_EINVAL);
+  EXPECT(tfan_export_state(nullptr, nullptr, 0, 7) == TFAN_EINVAL);
+  EXPECT(tfan_import_state(nullptr, nullptr, 0, 7, 0) == TFAN_EINVAL);
   tfan_destroy(nullptr);
   EXPECT(tfan_kernel_count() > 0);
   for (int k = -1; k <= tfan_kernel_count(); ++k) {

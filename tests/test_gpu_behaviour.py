@@ -57,14 +57,16 @@ def test_state_exchange_checks_its_arrays(gpu):
     p = workload_params("small_64")
     s = make(p)
     n = 64 * 64
-    need = int(s.lib.tfan_exchange_bytes(s.handle))
-    assert need == 7 * n * 4
+    need = int(s.lib.tfan_exchange_bytes(s.handle, 7))
+    assert need == 7 * n * 4 and int(s.lib.tfan_exchange_bytes(s.handle, 9)) == 9 * n * 4
     vp = ctypes.c_void_p
     host = np.zeros(7 * n, np.float32)
-    assert s.lib.tfan_export_state(s.handle, host.ctypes.data_as(vp), need) == T.TFAN_EINVAL
-    assert s.lib.tfan_import_state(s.handle, host.ctypes.data_as(vp), need, 0) == T.TFAN_EINVAL
+    assert s.lib.tfan_export_state(s.handle, host.ctypes.data_as(vp), need, 7) == T.TFAN_EINVAL
+    assert s.lib.tfan_import_state(s.handle, host.ctypes.data_as(vp), need, 7, 0) == T.TFAN_EINVAL
     dev = torch.zeros(7 * n, dtype=torch.float32, device="cuda")
-    assert s.lib.tfan_export_state(s.handle, vp(dev.data_ptr()), need - 4) == T.TFAN_ENOMEM
+    assert s.lib.tfan_export_state(s.handle, vp(dev.data_ptr()), need - 4, 7) == T.TFAN_ENOMEM
+    assert s.lib.tfan_export_state(s.handle, vp(dev.data_ptr()), 7 * n * 4, 9) == T.TFAN_ENOMEM
+    assert s.lib.tfan_import_state(s.handle, vp(dev.data_ptr()), need, 8, 0) == T.TFAN_EINVAL
     s.sync()
     x = torch.empty((7, 64, 64), dtype=torch.float32, device="cuda")
     s.export_state(x)
@@ -77,9 +79,10 @@ def test_state_exchange_checks_its_arrays(gpu):
     g = s.get_fields()
     assert s.step_count() == 7
     np.testing.assert_array_equal(g["qxx"], f["qxx"])
-    # populations restart at f^eq(rho0, u): density deviations are zero up to the
-    # float32 rounding of the shifted equilibrium (|u| ~ 1e-3 here)
-    np.testing.assert_allclose(g["rho_a"], 1.0, rtol=0, atol=1e-8)
+    # the import keeps the densities and gives back the velocities, up to the
+    # float32 rounding of the rebuilt populations
+    np.testing.assert_allclose(g["rho_a"], f["rho_a"], rtol=0, atol=1e-7)
+    np.testing.assert_allclose(g["u_a"], f["u_a"], rtol=1e-5, atol=1e-9)
 
 
 def test_health_flags(gpu):

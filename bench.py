@@ -79,6 +79,59 @@ def measured_traffic(kernel: str):
     return None if k is None else float(k["bytes_per_launch"])
 
 
+# Kernels whose HBM traffic profiles/traffic.json records (float32 populations,
+# default launch shape), by their name in the counter output.
+TRAFFIC_KERNELS = {"collide": "k_collide<false, float, 2>", "substeps": "k_fd_pair<40, 5>"}
+
+
+def write_traffic(root_dir: str, sites: int = 2048 * 2048):
+    """profiles/traffic.json from four rocprofv3 --pmc runs under root_dir:
+    pmc_step_FETCH / pmc_step_WRITE (this benchmark, FETCH_SIZE / WRITE_SIZE) and
+    pmc_copy_FETCH / pmc_copy_WRITE (--calibrate-copy 1024).  Each counter is scaled
+    by what it reads for the plain 1 GiB copy."""
+    import csv
+    import glob
+
+    def means(sub, counter):
+        (path,) = glob.glob(os.path.join(root_dir, sub, "*counter_collection.csv"))
+        acc = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                if name.startswith("__amd_rocclr_copyBuffer"):
+                    key = "copy"
+                else:
+                    key = next((k for k, v in TRAFFIC_KERNELS.items() if "::" + v + "(" in name), None)
+                if key:
+                    acc.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+    nbytes = 1 << 30
+    fetch, write = means("pmc_step_FETCH", "FETCH_SIZE"), means("pmc_step_WRITE", "WRITE_SIZE")
+    cf, cw = means("pmc_copy_FETCH", "FETCH_SIZE")["copy"][0], means("pmc_copy_WRITE", "WRITE_SIZE")["copy"][0]
+    fs, ws = nbytes / (cf * 1024), nbytes / (cw * 1024)
+    rec = {"source_hash": source_hash(),
+           "workload": "large_2048 (2048x2048, n_sub=5, default launch shape), bench.py --steps 25 --warmup 5 "
+                       "under rocprofv3 --pmc, one counter per run",
+           "calibration": {"kernel": "__amd_rocclr_copyBuffer, 1 GiB device copy (bench.py --calibrate-copy 1024)",
+                           "FETCH_SIZE_KiB_per_launch": round(cf, 1), "WRITE_SIZE_KiB_per_launch": round(cw, 1),
+                           "bytes_read": nbytes, "bytes_written": nbytes,
+                           "fetch_scale": round(fs, 4), "write_scale": round(ws, 4)},
+           "kernels": {}}
+    for key, kname in TRAFFIC_KERNELS.items():
+        (fk, nd), (wk, _) = fetch[key], write[key]
+        rd, wr = fk * 1024 * fs, wk * 1024 * ws
+        rec["kernels"][key] = {"kernel": kname, "dispatches": nd, "FETCH_SIZE_KiB": round(fk, 1),
+                               "WRITE_SIZE_KiB": round(wk, 1), "bytes_per_launch": int(round(rd + wr)),
+                               "bytes_per_site": round((rd + wr) / sites, 2),
+                               "read_bytes_per_site": round(rd / sites, 2), "write_bytes_per_site": round(wr / sites, 2)}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(params, ic, budget_s: float, single_core_s: float = 0.0):
     """The FP64 C oracle (oracle/coracle.c, OpenMP over rows), unchanged, on the same
     grid: whole coupled steps until the time budget is used, with every host thread;
@@ -401,7 +454,12 @@ def main():
                     help="launch shape collide_rows,fd_shape (default: the library's)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--write-traffic", default="", metavar="DIR",
+                    help="only write profiles/traffic.json from the four --pmc runs under DIR (no GPU)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.calibrate_copy:
         import torch
         torch.cuda.set_device(0)

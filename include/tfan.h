@@ -102,6 +102,7 @@ typedef struct tfan_diag {
   double elastic;      /* sum (K/2) |grad Q|^2, |grad Q|^2 = sum_kij (d_k Q_ij)^2 */
   double s_mean;       /* mean of S over sites, S = sqrt(Qxx^2 + Qxy^2) (Q = 2S(pp - I/2)) */
   double umax;         /* max over sites of max(|u_a|, |u_p|)                    */
+  double phi_absmax;   /* max over sites of |phi|                                */
 } tfan_diag;
 
 typedef struct tfan_sim tfan_sim;

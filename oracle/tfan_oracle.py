@@ -266,6 +266,12 @@ def solve_velocities(rho_a, m_a, G_a, rho_p, m_p, G_p, beta):
 # ----------------------------------------------------------------------------
 # The coupled step
 # ----------------------------------------------------------------------------
+def phi_extent(phi):
+    """Largest |phi| over the sites: how far the order parameter leaves its bulk
+    values +-1 (a health measure of a state, not an observable of the paper)."""
+    return float(np.abs(phi).max())
+
+
 class Oracle:
     """Plain FP64 solver.  State: pre-collision populations f_a, f_p [9, ny, nx]
     (the result of streaming), phi, Q components qxx, qxy [ny, nx], step counter."""
@@ -368,6 +374,7 @@ class Oracle:
             out[k] = float(obs[k].sum())
         out["s_mean"] = float(obs["S"].mean())
         out["umax"] = float(obs["speed"].max())
+        out["phi_absmax"] = phi_extent(self.phi)
         return out
 
     def free_energy(self) -> float:

@@ -32,7 +32,7 @@ class tfan_diag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("nonfinite", ctypes.c_int64)] + [
         (k, ctypes.c_double) for k in ("phi_sum", "phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p",
                                        "ke_c", "ua_sq", "uc_sq", "enstrophy_a", "enstrophy_c",
-                                       "elastic", "s_mean", "umax")]
+                                       "elastic", "s_mean", "umax", "phi_absmax")]
 
 
 class TfanError(RuntimeError):

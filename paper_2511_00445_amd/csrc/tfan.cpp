@@ -402,6 +402,7 @@ int tfan_diagnostics(tfan_sim* s, tfan_diag* out) {
   out->elastic = r[tfan::D_ELASTIC];
   out->s_mean = r[tfan::D_S] / (double)s->dp.n;
   out->umax = r[tfan::D_UMAX];
+  out->phi_absmax = r[tfan::D_PHIMAX];
   if (out->nonfinite > 0) return fail(s, TFAN_ENONFINITE, "state holds non-finite values");
   if (out->umax > 0.3) return fail(s, TFAN_EUNSTABLE, "max |u| exceeds 0.3");
   return TFAN_OK;

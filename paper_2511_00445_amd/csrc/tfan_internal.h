@@ -27,11 +27,12 @@ struct DevParams {
 
 // Number of float64 slots in one diagnostics record.
 constexpr int kDiagSlots = 16;
-// Slot order of the diagnostics record (the last is a maximum, the rest sums).
+// Slot order of the diagnostics record (the last two are maxima, the rest sums).
 enum DiagSlot {
   D_PHI = 0, D_PHI2, D_MASS_A, D_MASS_P, D_KE_A, D_KE_P, D_KE_C, D_UA2, D_UC2,
-  D_ENS_A, D_ENS_C, D_ELASTIC, D_S, D_NONFINITE, D_UNUSED, D_UMAX
+  D_ENS_A, D_ENS_C, D_ELASTIC, D_S, D_NONFINITE, D_PHIMAX, D_UMAX
 };
+constexpr bool diag_is_max(int k) { return k >= D_PHIMAX; }
 
 // Device buffers of one solver (all float32, each [ny][nx] plane n floats).
 struct DevState {

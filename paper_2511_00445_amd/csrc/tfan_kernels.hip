@@ -1312,14 +1312,14 @@ __device__ __forceinline__ void block_reduce_store(double acc[kDiagSlots], doubl
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kDiagSlots; ++k) {
-    const double v = (k == D_UMAX) ? wave_max(acc[k]) : wave_sum(acc[k]);
+    const double v = diag_is_max(k) ? wave_max(acc[k]) : wave_sum(acc[k]);
     if (lane == 0) red[wave][k] = v;
   }
   __syncthreads();
   if (threadIdx.x < kDiagSlots) {
     const int k = threadIdx.x;
     double v = red[0][k];
-    for (int w = 1; w < kDiagThreads / 64; ++w) v = (k == D_UMAX) ? fmax(v, red[w][k]) : v + red[w][k];
+    for (int w = 1; w < kDiagThreads / 64; ++w) v = diag_is_max(k) ? fmax(v, red[w][k]) : v + red[w][k];
     dst[k] = v;
   }
 }
@@ -1349,6 +1349,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DevParams P, DevState in,
     const double ph = in.phi[idx];
     acc[D_PHI] += ph;
     acc[D_PHI2] += ph * ph;
+    acc[D_PHIMAX] = fmax(acc[D_PHIMAX], fabs(ph));
     const double ra = P.rho0_d + (double)drho_a[idx], rp = P.rho0_d + (double)drho_p[idx];
     acc[D_MASS_A] += ra;
     acc[D_MASS_P] += rp;
@@ -1394,7 +1395,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
 #pragma unroll
     for (int k = 0; k < kDiagSlots; ++k) {
       const double v = partials[(size_t)b * kDiagSlots + k];
-      acc[k] = (k == D_UMAX) ? fmax(acc[k], v) : acc[k] + v;
+      acc[k] = diag_is_max(k) ? fmax(acc[k], v) : acc[k] + v;
     }
   }
   block_reduce_store(acc, out);

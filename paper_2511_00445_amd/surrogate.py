@@ -31,6 +31,13 @@ from .workloads import initial_fields
 K_STEPS = 50
 RELAX_STEPS = 25     # solver steps after each jump in the deploy loop
 TRAIN_STEPS = 12000  # Adam steps of the standard training run (batches of 8)
+# Bounds of an accepted surrogate state.  The solver's own trajectories keep |phi|
+# within a few percent of 1 (the bulk values) and |u| near 0.03-0.05 on the
+# deployment workload; a chain of network jumps can leave a few sites with phi
+# overshoots or velocity spikes that a whole-grid L2 check does not see and from
+# which the solver itself can diverge.
+PHI_LIMIT = 1.15
+U_LIMIT = 0.1
 # Training trajectories: 256 x 256 runs, pairs from steps TRAIN_T0 to TRAIN_T1, so
 # that the network has seen the early coarsening and the late, activity-arrested
 # domains it meets over long deployments.
@@ -146,7 +153,8 @@ class SurrogateRun:
     """A solver advanced by surrogate calls, checked against itself, with rollback."""
 
     def __init__(self, sim: Sim, net: Cnn, k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2,
-                 hold: int = 10, channels=(0, 1, 2), relax: int = 0, densities: str = "reset"):
+                 hold: int = 10, channels=(0, 1, 2), relax: int = 0, densities: str = "reset",
+                 phi_limit: float = PHI_LIMIT, u_limit: float = U_LIMIT):
         import torch
         if net.batch != 1 or (net.ny, net.nx) != (sim.ny, sim.nx):
             raise ValueError("the network must take one sample of the solver's grid")
@@ -164,6 +172,8 @@ class SurrogateRun:
         if densities not in ("keep", "reset"):
             raise ValueError("densities must be 'keep' or 'reset'")
         self.densities = densities
+        # a state is accepted only within these bounds (see PHI_LIMIT, U_LIMIT)
+        self.phi_limit, self.u_limit = float(phi_limit), float(u_limit)
         shape = (1, 7, sim.ny, sim.nx)
         self.x = torch.empty(shape, dtype=torch.float32, device="cuda")
         self.xp = torch.empty_like(self.x)
@@ -176,12 +186,30 @@ class SurrogateRun:
         self.good_step = None
         self.since_check = 0
         self.surrogate_calls = self.solver_calls = self.checks = self.fallbacks = 0
+        self.health_rollbacks = 0  # unhealthy states at the end of advance(), redone with the solver
+        self.relax_rollbacks = 0   # passed checks whose relax span left an unhealthy state
         self.plain_left = 0
         self.errors = []  # (step, relative L2 error) of every check
+
+    def _healthy(self) -> bool:
+        return self.sim.diagnostics()["status"] == 0
+
+    def _valid(self) -> bool:
+        """Healthy, and within the bounds a solver trajectory stays in."""
+        d = self.sim.diagnostics()
+        return d["status"] == 0 and d["phi_absmax"] <= self.phi_limit and d["umax"] <= self.u_limit
 
     def _mark_good(self):
         self.sim.export_state(self.good)
         self.good_step = self.sim.step_count()
+        self.since_check = 0
+
+    def _roll_back(self):
+        """Restore the last checked state; the solver redoes the span (plus `hold` calls)."""
+        self.fallbacks += 1
+        span = (self.sim.step_count() - self.good_step) // (self.k + self.relax) + 1
+        self.sim.import_state(self.good, self.good_step)
+        self.plain_left = span + self.hold
         self.since_check = 0
 
     def advance(self, steps: int):
@@ -190,6 +218,8 @@ class SurrogateRun:
             raise ValueError("steps must be a multiple of k + relax")
         target = self.sim.step_count() + steps
         if self.good_step is None:
+            if not self._healthy():
+                raise RuntimeError("the solver's state is unhealthy before the first surrogate call")
             self._mark_good()
         while self.sim.step_count() < target:
             if self.plain_left > 0:
@@ -197,6 +227,8 @@ class SurrogateRun:
                 self.solver_calls += 1
                 self.plain_left -= 1
                 if self.plain_left == 0:
+                    if not self._healthy():
+                        raise RuntimeError("the plain solver became unhealthy after a rollback")
                     self._mark_good()
                 continue
             self.sim.export_state(self.x[0])
@@ -207,32 +239,46 @@ class SurrogateRun:
                 self.sim.export_state(self.xs[0])
                 c = self.net.compare(self.x9[None, :7] if self.x9 is not None else self.xp, self.xs)
                 err = float(np.sqrt(c[self.channels, 0].sum() / c[self.channels, 1].sum()))
+                # the error judges (phi, Q) over the whole grid; the bounds catch
+                # what a few sites of the chained jumps carry (the solver keeps them)
+                if not self._valid():
+                    err = float("nan")
                 self.errors.append((self.sim.step_count(), err))
                 self.checks += 1
                 self.solver_calls += 1
                 if np.isfinite(err) and err <= self.tol:
                     if self.relax:
                         self.sim.step(self.relax)
-                    self._mark_good()
+                    if self._valid():
+                        self._mark_good()
+                    else:
+                        self.relax_rollbacks += 1
+                        self._roll_back()
                 else:
-                    # restore the last checked state; redo the span with the solver
-                    self.fallbacks += 1
-                    span = (self.sim.step_count() - self.good_step) // (self.k + self.relax) + 1
-                    self.sim.import_state(self.good, self.good_step)
-                    self.plain_left = span + self.hold
-                    self.since_check = 0
+                    self._roll_back()
             else:
                 self.sim.import_state(self.x9 if self.x9 is not None else self.xp[0], self.sim.step_count() + self.k)
                 self.surrogate_calls += 1
                 if self.relax:  # the solver smooths what the jump leaves at the grid scale
                     self.sim.step(self.relax)
+        # calls since the last check have not been judged: a state handed back must at
+        # least be healthy, else the span since the last checked state is redone with
+        # the solver
+        if self.since_check and not self._valid():
+            self.health_rollbacks += 1
+            self.sim.import_state(self.good, self.good_step)
+            self.sim.step(target - self.good_step)
+            self.solver_calls += (target - self.good_step) // (self.k + self.relax)
+            self._mark_good()
 
     def summary(self) -> dict:
         errs = [e for _, e in self.errors]
         return dict(surrogate_calls=self.surrogate_calls, solver_calls=self.solver_calls, checks=self.checks,
-                    fallbacks=self.fallbacks, failed_checks=sum(1 for e in errs if not e <= self.tol),
-                    max_check_error=max(errs) if errs else None,
-                    mean_check_error=float(np.mean(errs)) if errs else None)
+                    fallbacks=self.fallbacks, health_rollbacks=self.health_rollbacks,
+                    relax_rollbacks=self.relax_rollbacks, failed_checks=sum(1 for e in errs if not e <= self.tol),
+                    nonfinite_checks=sum(1 for e in errs if not np.isfinite(e)),
+                    max_check_error=float(np.nanmax(errs)) if np.isfinite(errs).any() else None,
+                    mean_check_error=float(np.nanmean(errs)) if np.isfinite(errs).any() else None)
 
 
 def train_surrogate(params: dict, seeds, t0: int, t1: int, steps: int, batch: int = 8, k: int = K_STEPS,

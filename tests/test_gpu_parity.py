@@ -120,7 +120,7 @@ def test_diagnostics_match_oracle(gpu):
     d, od = sim.diagnostics(), o.diagnostics()
     assert d["status"] == 0 and d["step"] == od["step"] == 60 and d["nonfinite"] == 0
     for k in ("phi_sq_sum", "mass_a", "mass_p", "ke_a", "ke_p", "ke_c", "ua_sq", "uc_sq",
-              "enstrophy_a", "enstrophy_c", "elastic", "s_mean", "umax"):
+              "enstrophy_a", "enstrophy_c", "elastic", "s_mean", "umax", "phi_absmax"):
         assert abs(d[k] - od[k]) <= 1e-4 * abs(od[k]) + 1e-12, (k, d[k], od[k])
     # phi mass: exact telescoping in the oracle; float32 drift measured and bounded
     assert abs(d["phi_sum"] - od["phi_sum"]) < 1e-4 * np.abs(ic["phi"]).sum()

@@ -127,6 +127,8 @@ MUTATIONS = [
     ("mixture velocity with swapped fractions", "site_observables",
      lambda phi, qxx, qxy, ra, rp, ua, up, K: O.site_observables(-phi, qxx, qxy, ra, rp, ua, up, K),
      T.test_p20_diagnostics_cellular_flow_vorticity, ()),
+    ("signed maximum of phi for its extent", "phi_extent", lambda phi: float(phi.max()),
+     T.test_p20_diagnostics_cellular_flow_vorticity, ()),
     ("scalar order without the square root", "scalar_order", lambda qxx, qxy: qxx ** 2 + qxy ** 2,
      T.test_p20_diagnostics_frank_energy_and_order, ()),
     ("LdG quartic coefficient A0 gamma", "landau_coefficients",

@@ -571,7 +571,7 @@ def test_p20_diagnostics_shear_flows():
                  ke_a=0.5 * rho0 * U * U * N / 2, ke_p=0.5 * rho0 * V * V * N / 2, ke_c=0.5 * W * W * N / 2,
                  ua_sq=U * U * N / 2, uc_sq=W * W * N / 2,
                  enstrophy_a=U * U * np.sin(k) ** 2 * N / 2, enstrophy_c=W * W * np.sin(k) ** 2 * N / 2,
-                 elastic=0.0, s_mean=0.0, umax=max(abs(U), abs(V)))
+                 elastic=0.0, s_mean=0.0, umax=max(abs(U), abs(V)), phi_absmax=abs(phibar))
     for key, val in exact.items():
         assert abs(d[key] - val) <= 1e-12 * max(abs(val), 1e-6 * N), (key, d[key], val)
     assert d["nonfinite"] == 0 and d["step"] == 0
@@ -594,6 +594,8 @@ def test_p20_diagnostics_cellular_flow_vorticity():
     assert abs(d["enstrophy_c"] - w * w * ens) < 1e-12 * ens
     # kinetic energy of the cellular flow: each component squares to a^2/4 on average
     assert abs(d["ua_sq"] - a * a * n * n / 2) < 1e-12 * a * a * n * n
+    # the largest |phi| of a uniform phi = -1/2 is 1/2, not its signed maximum
+    assert d["phi_absmax"] == 0.5
 
 
 def test_p20_diagnostics_frank_energy_and_order():
@@ -604,9 +606,10 @@ def test_p20_diagnostics_frank_energy_and_order():
     p = base_params(nx, ny, K=K)
     x, y = _modes(nx, ny)
     kx, ky = 2 * np.pi * mx / nx, 2 * np.pi * my / ny
-    o = _fresh(p, np.zeros((ny, nx)), e * np.cos(kx * x), f * np.sin(ky * y))
+    o = _fresh(p, -0.8 * np.cos(kx * x), e * np.cos(kx * x), f * np.sin(ky * y))
     d = o.diagnostics()
     N = nx * ny
+    assert abs(d["phi_absmax"] - 0.8) < 1e-15      # cos(kx x) = 1 at x = 0
     ex = K * (e * e * np.sin(kx) ** 2 + f * f * np.sin(ky) ** 2) * N / 2
     assert abs(d["elastic"] - ex) < 1e-12 * ex
     # a director pattern at fixed S: the scalar order is S at every site

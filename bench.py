@@ -80,8 +80,10 @@ def measured_traffic(kernel: str):
 
 
 # Kernels whose HBM traffic profiles/traffic.json records (float32 populations,
-# default launch shape), by their name in the counter output.
+# default launch shape), and a pattern of their name in the counter output (a
+# defaulted template argument may or may not be printed).
 TRAFFIC_KERNELS = {"collide": "k_collide<false, float, 2>", "substeps": "k_fd_pair<40, 5>"}
+TRAFFIC_NAMES = {"collide": r"::k_collide<false, float, 2(, false)?>\(", "substeps": r"::k_fd_pair<40, 5>\("}
 
 
 def write_traffic(root_dir: str, sites: int = 2048 * 2048):
@@ -91,6 +93,7 @@ def write_traffic(root_dir: str, sites: int = 2048 * 2048):
     by what it reads for the plain 1 GiB copy."""
     import csv
     import glob
+    import re
 
     def means(sub, counter):
         (path,) = glob.glob(os.path.join(root_dir, sub, "*counter_collection.csv"))
@@ -103,7 +106,7 @@ def write_traffic(root_dir: str, sites: int = 2048 * 2048):
                 if name.startswith("__amd_rocclr_copyBuffer"):
                     key = "copy"
                 else:
-                    key = next((k for k, v in TRAFFIC_KERNELS.items() if "::" + v + "(" in name), None)
+                    key = next((k for k, v in TRAFFIC_NAMES.items() if re.search(v, name)), None)
                 if key:
                     acc.setdefault(key, []).append(float(r["Counter_Value"]))
         return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}

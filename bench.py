@@ -298,6 +298,7 @@ def bench_surrogate(args):
         "L_within_5pct_through_step": within_until,
         "checks": r["checks"], "fallbacks": r["fallbacks"], "failed_checks": r["failed_checks"],
         "relax_rollbacks": r["relax_rollbacks"], "health_rollbacks": r["health_rollbacks"],
+        "deep_rollbacks": r["deep_rollbacks"],
         "max_check_error": r["max_check_error"], "train_seconds": round(train_s, 2),
         "train_loss": [round(float(np.mean(losses[:50])), 4), round(float(np.mean(losses[-200:])), 4)],
         "roofline": {"bound": "mfma", "kernel": "cnn_forward (6 convolutions)", "achieved": round(achieved, 1),

@@ -150,11 +150,18 @@ def prediction_errors(net: Cnn, X, T, channels=(0, 1, 2)):
 
 
 class SurrogateRun:
-    """A solver advanced by surrogate calls, checked against itself, with rollback."""
+    """A solver advanced by surrogate calls, checked against itself, with rollback.
+
+    Every `check_every`-th call runs the solver over the jump instead and compares
+    the two; a state is accepted only after a passed check and within the solver's
+    bounds.  The last `depth` accepted states are kept (with their densities): a
+    failed check rolls back to the newest one and the solver redoes the span plus
+    `hold` calls; if the solver itself fails from there, the run rolls back one
+    accepted state further."""
 
     def __init__(self, sim: Sim, net: Cnn, k: int = K_STEPS, check_every: int = 10, tol: float = 5e-2,
                  hold: int = 10, channels=(0, 1, 2), relax: int = 0, densities: str = "reset",
-                 phi_limit: float = PHI_LIMIT, u_limit: float = U_LIMIT):
+                 phi_limit: float = PHI_LIMIT, u_limit: float = U_LIMIT, depth: int = 2, device: str = "cuda"):
         import torch
         if net.batch != 1 or (net.ny, net.nx) != (sim.ny, sim.nx):
             raise ValueError("the network must take one sample of the solver's grid")
@@ -174,22 +181,29 @@ class SurrogateRun:
         self.densities = densities
         # a state is accepted only within these bounds (see PHI_LIMIT, U_LIMIT)
         self.phi_limit, self.u_limit = float(phi_limit), float(u_limit)
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
         shape = (1, 7, sim.ny, sim.nx)
-        self.x = torch.empty(shape, dtype=torch.float32, device="cuda")
+        self.x = torch.empty(shape, dtype=torch.float32, device=device)
         self.xp = torch.empty_like(self.x)
         self.xs = torch.empty_like(self.x)
         # jump target with zero density planes, for densities = "reset"
-        self.x9 = torch.zeros((9, sim.ny, sim.nx), dtype=torch.float32, device="cuda") if densities == "reset" else None
-        # last checked state with its densities: a rollback restores all but the
-        # populations' non-equilibrium part
-        self.good = torch.empty((9, sim.ny, sim.nx), dtype=torch.float32, device="cuda")
-        self.good_step = None
+        self.x9 = torch.zeros((9, sim.ny, sim.nx), dtype=torch.float32, device=device) if densities == "reset" else None
+        # accepted states with their densities: a rollback restores all but the
+        # populations' non-equilibrium part.  accepted = [(buffer index, step)], newest last
+        self.ring = [torch.empty((9, sim.ny, sim.nx), dtype=torch.float32, device=device) for _ in range(depth)]
+        self.accepted = []
         self.since_check = 0
         self.surrogate_calls = self.solver_calls = self.checks = self.fallbacks = 0
-        self.health_rollbacks = 0  # unhealthy states at the end of advance(), redone with the solver
-        self.relax_rollbacks = 0   # passed checks whose relax span left an unhealthy state
+        self.health_rollbacks = 0  # unjudged states at the end of advance() outside the bounds
+        self.relax_rollbacks = 0   # passed checks whose relax span left a state outside the bounds
+        self.deep_rollbacks = 0    # solver redos that failed, rolled back one accepted state further
         self.plain_left = 0
         self.errors = []  # (step, relative L2 error) of every check
+
+    @property
+    def good_step(self):
+        return self.accepted[-1][1] if self.accepted else None
 
     def _healthy(self) -> bool:
         return self.sim.diagnostics()["status"] == 0
@@ -200,36 +214,73 @@ class SurrogateRun:
         return d["status"] == 0 and d["phi_absmax"] <= self.phi_limit and d["umax"] <= self.u_limit
 
     def _mark_good(self):
-        self.sim.export_state(self.good)
-        self.good_step = self.sim.step_count()
+        used = {i for i, _ in self.accepted}
+        i = next(j for j in range(len(self.ring)) if j not in used) if len(used) < len(self.ring) \
+            else self.accepted[0][0]
+        self.sim.export_state(self.ring[i])
+        self.accepted = [a for a in self.accepted if a[0] != i] + [(i, self.sim.step_count())]
         self.since_check = 0
 
-    def _roll_back(self):
-        """Restore the last checked state; the solver redoes the span (plus `hold` calls)."""
-        self.fallbacks += 1
-        span = (self.sim.step_count() - self.good_step) // (self.k + self.relax) + 1
-        self.sim.import_state(self.good, self.good_step)
+    def _redo_from(self, back: int):
+        """Restore the accepted state `back` places before the newest (dropping the
+        newer ones); the solver redoes the span up to now plus `hold` calls."""
+        if back:
+            self.accepted = self.accepted[:-back]
+        i, step = self.accepted[-1]
+        span = -(-(self.sim.step_count() - step) // (self.k + self.relax))  # calls since, the last one partly done
+        self.sim.import_state(self.ring[i], step)
         self.plain_left = span + self.hold
         self.since_check = 0
 
+    def _roll_back(self):
+        self.fallbacks += 1
+        self._redo_from(0)
+
     def advance(self, steps: int):
         """Advance by `steps` lattice steps (a multiple of k + relax)."""
-        if steps % (self.k + self.relax):
+        call = self.k + self.relax
+        if steps % call:
             raise ValueError("steps must be a multiple of k + relax")
         target = self.sim.step_count() + steps
-        if self.good_step is None:
+        if not self.accepted:
             if not self._healthy():
                 raise RuntimeError("the solver's state is unhealthy before the first surrogate call")
             self._mark_good()
+        while True:
+            self._run_to(target)
+            # calls since the last check have not been judged: a state handed back
+            # must be within the bounds, else the solver redoes them to the target
+            if self.since_check and not self._valid():
+                self.health_rollbacks += 1
+                i, step = self.accepted[-1]
+                self.sim.import_state(self.ring[i], step)
+                self.plain_left = (target - step) // call
+                self.since_check = 0
+                continue
+            # a solver redo still under way must at least be healthy
+            if self.plain_left and not self._healthy():
+                self._solver_failed()
+                continue
+            return
+
+    def _solver_failed(self):
+        if len(self.accepted) < 2:
+            raise RuntimeError("the solver became unhealthy from the oldest accepted state")
+        self.deep_rollbacks += 1
+        self._redo_from(1)
+
+    def _run_to(self, target: int):
+        call = self.k + self.relax
         while self.sim.step_count() < target:
             if self.plain_left > 0:
-                self.sim.step(self.k + self.relax)
+                self.sim.step(call)
                 self.solver_calls += 1
                 self.plain_left -= 1
                 if self.plain_left == 0:
-                    if not self._healthy():
-                        raise RuntimeError("the plain solver became unhealthy after a rollback")
-                    self._mark_good()
+                    if self._healthy():
+                        self._mark_good()
+                    else:
+                        self._solver_failed()
                 continue
             self.sim.export_state(self.x[0])
             self.net.forward(self.x, self.x9[None, :7] if self.x9 is not None else self.xp)
@@ -261,21 +312,12 @@ class SurrogateRun:
                 self.surrogate_calls += 1
                 if self.relax:  # the solver smooths what the jump leaves at the grid scale
                     self.sim.step(self.relax)
-        # calls since the last check have not been judged: a state handed back must at
-        # least be healthy, else the span since the last checked state is redone with
-        # the solver
-        if self.since_check and not self._valid():
-            self.health_rollbacks += 1
-            self.sim.import_state(self.good, self.good_step)
-            self.sim.step(target - self.good_step)
-            self.solver_calls += (target - self.good_step) // (self.k + self.relax)
-            self._mark_good()
 
     def summary(self) -> dict:
         errs = [e for _, e in self.errors]
         return dict(surrogate_calls=self.surrogate_calls, solver_calls=self.solver_calls, checks=self.checks,
                     fallbacks=self.fallbacks, health_rollbacks=self.health_rollbacks,
-                    relax_rollbacks=self.relax_rollbacks, failed_checks=sum(1 for e in errs if not e <= self.tol),
+                    relax_rollbacks=self.relax_rollbacks, deep_rollbacks=self.deep_rollbacks, failed_checks=sum(1 for e in errs if not e <= self.tol),
                     nonfinite_checks=sum(1 for e in errs if not np.isfinite(e)),
                     max_check_error=float(np.nanmax(errs)) if np.isfinite(errs).any() else None,
                     mean_check_error=float(np.nanmean(errs)) if np.isfinite(errs).any() else None)

@@ -263,6 +263,13 @@ def solve_velocities(rho_a, m_a, G_a, rho_p, m_p, G_p, beta):
     return np.moveaxis(sol[..., 0, :], -1, 0), np.moveaxis(sol[..., 1, :], -1, 0)
 
 
+def guo_momenta(rho_a, u_a, G_a, rho_p, u_p, G_p, beta):
+    """The momenta m_a, m_p whose Guo velocities (solve_velocities) are u_a, u_p:
+    the two balance equations of solve_velocities solved for m instead of u."""
+    drag = beta * (u_p - u_a)
+    return rho_a * u_a - 0.5 * (G_a + drag), rho_p * u_p - 0.5 * (G_p - drag)
+
+
 # ----------------------------------------------------------------------------
 # The coupled step
 # ----------------------------------------------------------------------------
@@ -304,8 +311,29 @@ class Oracle:
         self.f_p = equilibrium(rho, up)
         self.step_count = 0
 
+    def import_state(self, phi, qxx, qxy, u_a, u_p, rho_a, rho_p, step: int):
+        """A state rebuilt from macroscopic fields (the surrogate's reconstruction, not
+        a step of the paper): phi and Q as given; pre-collision populations at
+        equilibrium with the given densities and with the momenta whose Guo
+        velocities, under the forces of the given phi and Q, are the given ones."""
+        shape = (self.p["ny"], self.p["nx"])
+        self.phi = np.array(phi, np.float64).reshape(shape).copy()
+        self.qxx = np.array(qxx, np.float64).reshape(shape).copy()
+        self.qxy = np.array(qxy, np.float64).reshape(shape).copy()
+        ua = np.array(u_a, np.float64).reshape((2,) + shape)
+        up = np.array(u_p, np.float64).reshape((2,) + shape)
+        ra = np.array(rho_a, np.float64).reshape(shape)
+        rp = np.array(rho_p, np.float64).reshape(shape)
+        fr = self.forces()
+        m_a, m_p = guo_momenta(ra, ua, fr["G_a"], rp, up, fr["G_p"], self.p["gamma"] * fr["c1"] * fr["c2"])
+        self.f_a = equilibrium(ra, m_a / ra)
+        self.f_p = equilibrium(rp, m_p / rp)
+        self.step_count = int(step)
+
     # -- steps 1-4: fractions, potentials, stresses, forces, velocities ---------
-    def macroscopic(self):
+    def forces(self):
+        """Fractions, chemical potential, Q, H, stress and the non-drag forces G_a, G_p
+        of the current phi and Q."""
         p = self.p
         phi = self.phi
         c1 = 0.5 * (1.0 + phi)
@@ -317,8 +345,12 @@ class Oracle:
         sigma = elastic_stress(Q, H, p["lam"], p["K"]) + active_stress(Q, c1, p["zeta"])
         F_el_act = divergence(sigma)
         F_ch = capillary_force(phi, mu)
-        G_a = F_el_act + c1 * F_ch
-        G_p = c2 * F_ch
+        return dict(c1=c1, c2=c2, mu=mu, Q=Q, H=H, sigma=sigma, G_a=F_el_act + c1 * F_ch, G_p=c2 * F_ch)
+
+    def macroscopic(self):
+        p = self.p
+        fr = self.forces()
+        c1, c2, mu, Q, H, sigma, G_a, G_p = (fr[k] for k in ("c1", "c2", "mu", "Q", "H", "sigma", "G_a", "G_p"))
         rho_a, m_a = moments(self.f_a)
         rho_p, m_p = moments(self.f_p)
         beta = p["gamma"] * c1 * c2

@@ -143,3 +143,31 @@ def test_full_size_sampled_windows(gpu, name, steps):
         wf, xs, ys = window_oracle(p, ic, cx, cy, 8, steps)
         sub = {k: v[..., ys[:, None], xs[None, :]] for k, v in gf.items()}
         compare(sub, wf, label=f"{name} window at ({cx},{cy})")
+
+
+@pytest.mark.parametrize("steps", [0, 10])
+def test_import_then_steps_match_oracle(gpu, steps):
+    """A state imported through the nine-plane exchange (phi, Q, velocities and
+    densities; the populations rebuilt by the import kernel) and then stepped,
+    against the oracle's reconstruction of the same float32 inputs (its
+    import_state, pinned by P23) stepped alike.  Relaxation times away from 1 make
+    the collision see the rebuilt populations' non-equilibrium part."""
+    import torch
+    from paper_2511_00445_amd import Sim
+    say(f"case: import then {steps} steps 48x40")
+    nx, ny = 48, 40
+    p = base_params(nx, ny, zeta=0.02, gamma=0.2, lam=0.9, tau_a=0.8, tau_p=1.3)
+    rng = np.random.default_rng(31)
+    ic = initial_fields(nx, ny, seed=31, phi_noise=0.3, S0=0.2)
+    x = np.concatenate([ic["phi"][None], ic["qxx"][None], ic["qxy"][None],
+                        0.01 * rng.normal(size=(4, ny, nx)), 1e-3 * rng.normal(size=(2, ny, nx))]).astype(np.float32)
+    sim = Sim(p)
+    sim.import_state(torch.from_numpy(x).cuda(), 0)
+    sim.step(steps)
+    xd = x.astype(np.float64)
+    o = Oracle(p)
+    o.import_state(xd[0], xd[1], xd[2], xd[3:5], xd[5:7], 1.0 + xd[7], 1.0 + xd[8], 0)
+    o.step(steps)
+    assert sim.step_count() == o.step_count == steps
+    errs = compare(sim.get_fields(), o.get_fields(), label=f"import + {steps} steps")
+    say(f"relative L2: {errs}")

@@ -127,6 +127,12 @@ MUTATIONS = [
     ("mixture velocity with swapped fractions", "site_observables",
      lambda phi, qxx, qxy, ra, rp, ua, up, K: O.site_observables(-phi, qxx, qxy, ra, rp, ua, up, K),
      T.test_p20_diagnostics_cellular_flow_vorticity, ()),
+    ("import momenta with the half force added", "guo_momenta",
+     lambda ra, ua, Ga, rp, up, Gp, beta: (ra * ua + 0.5 * (Ga + beta * (up - ua)), rp * up + 0.5 * (Gp - beta * (up - ua))),
+     T.test_p23_import_gives_back_densities_and_velocities, ()),
+    ("import momenta without the drag", "guo_momenta",
+     lambda ra, ua, Ga, rp, up, Gp, beta: (ra * ua - 0.5 * Ga, rp * up - 0.5 * Gp),
+     T.test_p23_import_gives_back_densities_and_velocities, ()),
     ("signed maximum of phi for its extent", "phi_extent", lambda phi: float(phi.max()),
      T.test_p20_diagnostics_cellular_flow_vorticity, ()),
     ("scalar order without the square root", "scalar_order", lambda qxx, qxy: qxx ** 2 + qxy ** 2,

@@ -688,3 +688,30 @@ def test_p22_capillary_force_term_by_term(m1, m2):
     np.testing.assert_allclose(F[1], 0.0, atol=1e-17)
     if m2 == N // 2:
         np.testing.assert_allclose(F[0], 2 * a * b * np.sin(k1) * np.cos(k1 * x) * (-1.0) ** x, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P23: the state reconstruction of the surrogate's import (not a step of the
+# paper).  The pre-collision populations it builds must give back, through the
+# step's own Guo velocity solve (solve_velocities, pinned by P3 and P5) and the
+# equilibrium moments (P1), exactly the densities and velocities it was given,
+# under forces large enough that dropping or flipping the half force shows.
+def test_p23_import_gives_back_densities_and_velocities():
+    nx, ny = 24, 20
+    p = base_params(nx, ny, zeta=0.02, gamma=0.3, lam=0.9)
+    rng = np.random.default_rng(23)
+    x, y = _modes(nx, ny)
+    phi = 0.8 * np.cos(2 * np.pi * x / nx) + 0.05 * rng.normal(size=(ny, nx))
+    qxx, qxy = 0.1 * rng.normal(size=(2, ny, nx))
+    ua, up = 0.01 * rng.normal(size=(2, 2, ny, nx))
+    ra, rp = 1.0 + 1e-3 * rng.normal(size=(2, ny, nx))
+    o = O.Oracle(p)
+    o.import_state(phi, qxx, qxy, ua, up, ra, rp, step=7)
+    f = o.get_fields()
+    assert o.step_count == 7
+    np.testing.assert_array_equal(f["phi"], phi)
+    for key, want in (("u_a", ua), ("u_p", up), ("rho_a", ra), ("rho_p", rp)):
+        assert np.abs(f[key] - want).max() < 1e-14, key
+    # the forces are not negligible: populations at f^eq(rho, u) would be off by G/2
+    fr = o.forces()
+    assert np.abs(0.5 * fr["G_a"] / ra).max() > 1e-4

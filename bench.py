@@ -86,7 +86,7 @@ TRAFFIC_KERNELS = {"collide": "k_collide<false, float, 2>", "substeps": "k_fd_pa
 TRAFFIC_NAMES = {"collide": r"::k_collide<false, float, 2(, false)?>\(", "substeps": r"::k_fd_pair<40, 5>\("}
 
 
-def write_traffic(root_dir: str, sites: int = 2048 * 2048):
+def write_traffic(root_dir: str, sites: int = 2048 * 2048, out_path: str = ""):
     """profiles/traffic.json from four rocprofv3 --pmc runs under root_dir:
     pmc_step_FETCH / pmc_step_WRITE (this benchmark, FETCH_SIZE / WRITE_SIZE) and
     pmc_copy_FETCH / pmc_copy_WRITE (--calibrate-copy 1024).  Each counter is scaled
@@ -130,9 +130,10 @@ def write_traffic(root_dir: str, sites: int = 2048 * 2048):
                                "WRITE_SIZE_KiB": round(wk, 1), "bytes_per_launch": int(round(rd + wr)),
                                "bytes_per_site": round((rd + wr) / sites, 2),
                                "read_bytes_per_site": round(rd / sites, 2), "write_bytes_per_site": round(wr / sites, 2)}
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+    with open(out_path or os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
+    return rec
 
 
 def cpu_baseline(params, ic, budget_s: float, single_core_s: float = 0.0):

@@ -45,3 +45,36 @@ def test_traffic_record_matches_sources_or_is_ignored():
     b = _bench()
     t = b.measured_traffic("collide")
     assert t is None or t > 0
+
+
+def test_traffic_summary_from_counter_files(tmp_path):
+    """bench.py --write-traffic: per-launch HBM bytes = FETCH_SIZE and WRITE_SIZE (KiB)
+    scaled by what each counter reads for the 1 GiB copy, averaged over dispatches;
+    kernel names match with or without the defaulted template argument."""
+    import csv
+    import bench
+
+    def put(sub, counter, rows):
+        d = tmp_path / sub
+        d.mkdir()
+        with open(d / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+            for i, (name, v) in enumerate(rows):
+                w.writerow([i, name, counter, v])
+
+    col = "void tfan::(anonymous namespace)::k_collide<false, float, 2, false>(tfan::DevParams, ...)"
+    col_true = "void tfan::(anonymous namespace)::k_collide<true, float, 2, false>(tfan::DevParams, ...)"
+    fd = "void tfan::(anonymous namespace)::k_fd_pair<40, 5>(tfan::DevParams, ...)"
+    put("pmc_step_FETCH", "FETCH_SIZE", [(col, 100.0), (col, 120.0), (col_true, 999.0), (fd, 10.0)])
+    put("pmc_step_WRITE", "WRITE_SIZE", [(col, 200.0), (col, 200.0), (fd, 20.0)])
+    put("pmc_copy_FETCH", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 524288.0)] * 3)
+    put("pmc_copy_WRITE", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", 1048576.0)] * 3)
+    rec = bench.write_traffic(str(tmp_path), sites=1024, out_path=str(tmp_path / "t.json"))
+    assert rec["calibration"]["fetch_scale"] == 2.0 and rec["calibration"]["write_scale"] == 1.0
+    c = rec["kernels"]["collide"]
+    assert c["dispatches"] == 2
+    assert c["bytes_per_launch"] == (110.0 * 2.0 + 200.0) * 1024
+    assert c["bytes_per_site"] == round((110.0 * 2.0 + 200.0), 2)
+    assert rec["kernels"]["substeps"]["bytes_per_launch"] == (10.0 * 2.0 + 20.0) * 1024
+    assert rec["source_hash"] == bench.source_hash()
